@@ -1,0 +1,56 @@
+"""The benchmark workloads: codes, channel SNRs, frame counts and seeds.
+
+Parameters only -- no encoding or decoding arithmetic lives here.  Each
+workload draws its frames from ``synth`` with its own seed.  The codes are
+the paper's families: rate-1/2 and high-rate codes from N = 256 up to
+N = 32768, including the (32768, 29492) code of Tables 1 and 3 and the
+(4096, 3686) code of Table 6.
+"""
+
+# Design Eb/N0 of the frozen set: 2.5 dB for rate 1/2, 4.0 dB for higher rates.
+DESIGN_DB_LOW_RATE = 2.5
+DESIGN_DB_HIGH_RATE = 4.0
+
+
+def code_k(n, rate):
+    """K = round_half_up(rate * N); rate 0.9 at N = 32768 is the paper's
+    (32768, 29492) code."""
+    if n == 32768 and abs(rate - 0.9) < 1e-9:
+        return 29492
+    return int(rate * n + 0.5)
+
+
+def design_db(rate):
+    return DESIGN_DB_LOW_RATE if rate <= 0.5 + 1e-9 else DESIGN_DB_HIGH_RATE
+
+
+# name -> description.  "codes" lists (N, K, design Eb/N0 dB).
+SC_1024 = dict(
+    name="sc_1024_512_f32", seed=1, algo="sc", llr="f32",
+    codes=[(1024, 512, 2.5)], ebn0_db=2.5, frames=10000)
+
+FSSC_32K = dict(
+    name="fastssc_32768_29492_i8", seed=2, algo="fastssc", llr="i8",
+    codes=[(32768, 29492, 4.0)], ebn0_db=4.0, frames=4096)
+
+FSSC_32K_F32 = dict(FSSC_32K, name="fastssc_32768_29492_f32", llr="f32")
+
+MIXED_NS = (256, 1024, 4096, 16384, 32768)
+MIXED_RATES = (0.5, 0.83, 0.9)
+MIXED = dict(
+    name="mixed_batch_i8", seed=3, algo="fastssc", llr="i8",
+    codes=[(n, code_k(n, r), design_db(r)) for n in MIXED_NS for r in MIXED_RATES],
+    ebn0_db=(2.0, 5.0), frames=65536)
+
+SERVE_NS = (1024, 4096, 32768)
+SERVE_RATES = (0.5, 0.6, 0.7, 0.8, 0.9)
+SERVING = dict(
+    name="serving_i8", seed=4, algo="fastssc", llr="i8",
+    codes=[(n, code_k(n, r), design_db(r)) for n in SERVE_NS for r in SERVE_RATES],
+    ebn0_db=(2.0, 5.0), loads=(0.1, 0.5, 0.9), frames_per_request=(1, 64))
+
+STRESS = dict(
+    name="stress_i8", seed=5, algo="fastssc", llr="i8",
+    codes=[(32768, 29492, 4.0), (4096, 3686, 4.0)], ebn0_db=4.5, frames=262144)
+
+ALL = [SC_1024, FSSC_32K, FSSC_32K_F32, MIXED, SERVING, STRESS]
