@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark: Fast-SSC decoding of the (32768, 29492) polar code, int8 LLRs.
+
+One step = one batched decode launch of 4,096 frames (channel LLRs already
+resident in HBM), the workload on which the paper quotes its 26 us / 1.13
+Gb/s single-core figure for this code.  Prints one JSON line:
+
+  value        information throughput (Gb/s) of the batched decode;
+  latency_us   p50/p99 frame latency of a batched launch (submit -> done);
+  plain        the same frames decoded with one launch per frame;
+  roofline     algorithmic HBM bytes (LLR in + info bits out) per launch
+               over the decode kernel's mean duration vs 8 TB/s;
+  cpu_baseline the CPU oracle on a bounded sample on this host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "info Gbps/GPU + p50/p99 frame latency (µs), (32768,29492) int8 vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def make_inputs(code, seed, frames, ebn0_db):
+    from paper_1504_00353_amd import synth
+    fr = code.frozen()
+    idx = np.arange(frames)
+    bits = synth.info_bits(seed, idx, code.k)
+    x = synth.unpack_bits(code.encode(synth.pack_bits(bits)), code.n)
+    z = synth.noise(seed, idx, code.n)
+    llr = synth.quantize6(synth.awgn_llr(x, z, ebn0_db, code.k / code.n))
+    return fr, bits, llr
+
+
+def percentile(v, p):
+    return float(np.percentile(np.asarray(v, np.float64), p))
+
+
+def cpu_baseline(frozen, llr, seconds=10.0):
+    """Plain CPU oracle (int8 Fast-SSC) on this host: all-core throughput
+    over repeated passes of a frame sample, plus a one-core latency."""
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    sample = llr[:512]
+    # one core
+    t0 = time.perf_counter()
+    oracle.decode(frozen, sample[:32], "fastssc", nthreads=1)
+    one_core_us = (time.perf_counter() - t0) / 32 * 1e6
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        oracle.decode(frozen, sample, "fastssc", nthreads=threads)
+        done += sample.shape[0]
+    dt = time.perf_counter() - t0
+    return done, dt, threads, one_core_us
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=4096)
+    ap.add_argument("--plain-frames", type=int, default=256)
+    ap.add_argument("--latency-runs", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py decodes on one GPU only: frames are independent, so more GPUs would "
+              "each run this same single-GPU decode on their own share (no collectives); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1504_00353_amd import Code, synth
+
+    n, k, design, ebn0 = 32768, 29492, 4.0, 4.0
+    frames = args.frames
+    code = Code(n, k, design, algo="fastssc", llr="i8")
+    frozen, info, llr_np = make_inputs(code, seed=2, frames=frames, ebn0_db=ebn0)
+    dev = torch.device("cuda", 0)
+    llr = torch.from_numpy(llr_np).to(dev)
+    out = torch.empty((frames, code.row_bytes), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        code.decode(llr, out=out)
+    torch.cuda.synchronize()
+
+    # timed region: K batched launches, events on the launch stream
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        code.decode(llr, out=out)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    ms_per_step = wall * 1e3 / args.steps
+    info_bits = float(k) * frames * args.steps
+    gbps = info_bits / wall / 1e9
+
+    decoded = synth.unpack_bits(out.cpu().numpy(), k)
+    fer = float(np.mean((decoded != info).any(axis=1)))
+
+    # batched frame latency: submit -> completion of a launch, one at a time
+    lat = []
+    for _ in range(args.latency_runs):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        code.decode(llr, out=out)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t) * 1e6)
+
+    # plain: one launch per frame, back to back, same frames
+    pf = min(args.plain_frames, frames)
+    outs1 = torch.empty((pf, code.row_bytes), dtype=torch.uint8, device=dev)
+    for i in range(3):
+        code.decode(llr[i:i + 1], out=outs1[i:i + 1])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(pf):
+        code.decode(llr[i:i + 1], out=outs1[i:i + 1])
+    torch.cuda.synchronize()
+    plain_wall = time.perf_counter() - t
+    plain_gbps = float(k) * pf / plain_wall / 1e9
+    assert torch.equal(outs1, out[:pf]), "plain and batched decodes differ"
+    plat = []
+    for i in range(min(pf, 100)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        code.decode(llr[i:i + 1], out=outs1[i:i + 1])
+        torch.cuda.synchronize()
+        plat.append((time.perf_counter() - t) * 1e6)
+
+    bytes_per_frame = n * 1 + (k + 7) // 8
+    mean_kernel_s = float(np.mean(kernel_ms)) / 1e3
+    achieved = bytes_per_frame * frames / mean_kernel_s / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": round(gbps, 3),
+        "unit": "Gbps",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic: uniform info bits, BPSK over AWGN at 4.0 dB, 6-bit LLRs in int8",
+        "config": {"workload": "fastssc_32768_29492_i8", "N": n, "K": k, "design_ebn0_db": design,
+                   "ebn0_db": ebn0, "frames_per_step": frames, "algo": "fast-ssc"},
+        "latency_us": {"p50": round(percentile(lat, 50), 2), "p99": round(percentile(lat, 99), 2),
+                       "what": "batched launch of %d frames, submit to completion" % frames},
+        "plain": {"value": round(plain_gbps, 4), "unit": "Gbps", "frames": pf,
+                  "latency_us": {"p50": round(percentile(plat, 50), 2), "p99": round(percentile(plat, 99), 2)},
+                  "bits_equal_batched": True},
+        "fer": fer,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "decode_kernel<int8>", "bytes_per_frame": bytes_per_frame,
+                     "mean_kernel_ms": round(mean_kernel_s * 1e3, 4)},
+    }
+    if not args.no_cpu:
+        done, dt, threads, one_core_us = cpu_baseline(frozen, llr_np, args.cpu_seconds)
+        result["cpu_baseline"] = {"value": round(done * k / dt / 1e9, 5), "unit": "Gbps", "cores": threads,
+                                  "kind": "oracle",
+                                  "sample": "%d frames (512 distinct, repeated) of this workload, int8 Fast-SSC, "
+                                            "%.1f s" % (done, dt),
+                                  "one_core_latency_us": round(one_core_us, 1)}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,140 @@
+/*
+ * libpolar -- Fast-SSC and SC decoding of polar codes on AMD Instinct MI355X
+ * (gfx950).  C ABI: plain pointers and sizes, no exceptions cross it.
+ *
+ * The decoder is the one of Giard et al., "Low-Latency Software Polar
+ * Decoders": a depth-first walk of the pruned decoder tree (Sec. II-B, II-C)
+ * with the min-sum f of eq. (1), the g of eq. (2) and the combine of eq. (3),
+ * stopping at Rate-0 and Rate-1 nodes (Sec. II-D) and at repetition and
+ * single-parity-check nodes (Sec. II-E).  LLRs are 8-bit saturating fixed
+ * point (Sec. III-A.1, Listing 4: values in [-127, 127], g saturates) or
+ * IEEE binary32.
+ *
+ * Conventions shared by every entry point:
+ *   - natural (not bit-reversed) indexing (Sec. II-A); frozen bits are 0;
+ *   - an LLR is ln P(x=0)/P(x=1): positive favours bit 0; the hard decision
+ *     of a value v is 1 iff v < 0 (so zero decides 0);
+ *   - packed bit rows are LSB first: bit j of a row is (row[j/8] >> (j%8)) & 1;
+ *   - N is a power of two in [2, 32768] and 1 <= K <= N;
+ *   - functions returning polar_code* return NULL on error and record the
+ *     reason for polar_last_status() (thread local); functions returning
+ *     polar_status record it too.
+ * All functions are thread safe on distinct codes, and on one code once it
+ * is prepared (decode/encode/introspection only read it).
+ */
+#ifndef POLAR_H
+#define POLAR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct polar_code polar_code; /* opaque; owned by the library */
+
+typedef enum {
+  POLAR_OK = 0,
+  POLAR_EINVAL = 1,  /* bad argument: size, range, NULL pointer, alignment */
+  POLAR_ENOMEM = 2,  /* host or device allocation failed, or the code needs
+                        more on-chip memory than the device offers */
+  POLAR_EDEVICE = 3, /* a HIP call failed (launch error, no device) */
+  POLAR_ESTATE = 4   /* call out of order: e.g. decode before prepare,
+                        configure after prepare */
+} polar_status;
+
+typedef enum { POLAR_ALGO_FASTSSC = 0, POLAR_ALGO_SC = 1 } polar_algo;
+typedef enum { POLAR_LLR_I8 = 0, POLAR_LLR_F32 = 1 } polar_llr;
+
+/* Node functions reported by polar_schedule(), named after Listing 1. */
+typedef enum {
+  POLAR_OP_F = 0,          /* eq. (1) to the left child */
+  POLAR_OP_G = 1,          /* eq. (2) to the right child */
+  POLAR_OP_G_0R = 2,       /* eq. (2) when the left child is Rate-0 */
+  POLAR_OP_COMBINE = 3,    /* eq. (3) */
+  POLAR_OP_COMBINE_0R = 4, /* eq. (3) when the left child is Rate-0 */
+  POLAR_OP_INFO = 5,       /* Rate-1 node: eq. (4) on every bit */
+  POLAR_OP_REP = 6,        /* repetition node (Sec. II-E) */
+  POLAR_OP_SPC = 7         /* single-parity-check node (Sec. II-E) */
+} polar_op_kind;
+
+/* Builds an (N, K) code: the N-K least reliable bit channels are frozen
+ * (Sec. II-A), reliability being the Bhattacharyya parameter of BPSK over
+ * AWGN at the design Eb/N0 (dB) propagated through the polarising kernel
+ * (z -> 2z - z^2 for the first child, z -> z^2 for the second; ties go to
+ * the higher index as information bit).  Also builds the decoder schedule.
+ * The code starts configured as Fast-SSC with int8 LLRs.  Host only.
+ * Errors: POLAR_EINVAL (N not a power of two in [2, 32768], K outside
+ * [1, N]), POLAR_ENOMEM. */
+polar_code* polar_construct(int n, int k, double design_ebn0_db);
+
+/* Builds a code from an explicit frozen mask: frozen[i] in {0, 1} for
+ * i < N (1 = frozen, e.g. Fig. 2's (8,5) code is {1,1,0,0,1,0,0,0}).
+ * K = N - sum(frozen) must be >= 1.  The mask is copied. */
+polar_code* polar_construct_mask(int n, const uint8_t* frozen);
+
+/* Selects the algorithm (polar_algo) and LLR type (polar_llr).  Must be
+ * called before polar_prepare(); POLAR_ESTATE afterwards. */
+polar_status polar_configure(polar_code* code, int algo, int llr_type);
+
+/* Uploads the schedule to the current HIP device and sizes the launch for
+ * it.  Synchronous; allocates device memory; call it before any capture.
+ * Errors: POLAR_EDEVICE (no device / HIP failure), POLAR_ENOMEM (device
+ * allocation, or the decoder's on-chip working set does not fit the
+ * device's LDS), POLAR_ESTATE (already prepared). */
+polar_status polar_prepare(polar_code* code);
+
+/* Frees host and device memory of the code.  NULL is a no-op.  The caller
+ * must make sure no decode on the code is still running. */
+void polar_destroy(polar_code* code);
+
+polar_status polar_last_status(void);
+const char* polar_strerror(polar_status status);
+
+int polar_n(const polar_code* code); /* 0 for NULL */
+int polar_k(const polar_code* code); /* 0 for NULL */
+
+/* Copies the frozen mask (N bytes of 0/1) to host memory out. */
+polar_status polar_frozen_mask(const polar_code* code, uint8_t* out);
+
+/* The node functions one decode runs, in order (the form of Listing 1):
+ * kinds[i] is a polar_op_kind, sizes[i] the node size N_v, offsets[i] the
+ * index of the node's first bit.  Plain SC reports its full walk.  Writes at
+ * most cap entries to each non-NULL array and sets *n_ops to the total. */
+polar_status polar_schedule(const polar_code* code, int32_t* kinds, int32_t* sizes,
+                            int32_t* offsets, int cap, int* n_ops);
+
+/* Host encoder: x = u G_N (Sec. II-A) with u_A taken from info (packed
+ * rows of ceil(K/8) bytes, information bits in increasing index order) and
+ * u_F = 0.  Writes packed rows of ceil(N/8) bytes to x.  Host memory. */
+polar_status polar_encode(const polar_code* code, const uint8_t* info, int nframes, uint8_t* x);
+
+/* Decodes nframes frames on the given HIP stream (hipStream_t, NULL = the
+ * default stream).  Asynchronous: never allocates, frees or synchronises,
+ * so it can be captured in a HIP graph.
+ *   llr : device memory, [nframes][N] of int8 or float (as configured),
+ *         natural index order.  int8 -128 is read as -127.
+ *   bits: device memory, [nframes][ceil(K/8)] bytes: u_hat over the
+ *         information set in increasing index order, LSB first, pad bits 0.
+ * Both buffers belong to the caller and must stay alive until the stream
+ * has run the decode.  llr must be 4-byte aligned (16 recommended).
+ * nframes == 0 is a no-op.  Errors: POLAR_EINVAL (NULL buffers with
+ * nframes > 0, nframes < 0, misaligned llr), POLAR_ESTATE (not prepared),
+ * POLAR_EDEVICE (launch failed).  Kernel faults surface at the caller's
+ * next synchronisation. */
+polar_status polar_decode(const polar_code* code, const void* llr, int nframes, uint8_t* bits,
+                          void* stream);
+
+/* polar_decode plus a trace of the intermediate LLRs: for every frame,
+ * trace[frame][i] (int8 or float, [nframes][N], device memory) receives the
+ * LLR input alpha_v of the decision node (Rate-1, repetition or SPC leaf,
+ * or single bit in SC) that covers index i; indices under Rate-0 nodes are
+ * left untouched.  Slower; meant for parity tests. */
+polar_status polar_decode_trace(const polar_code* code, const void* llr, int nframes, uint8_t* bits,
+                                void* trace, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POLAR_H */

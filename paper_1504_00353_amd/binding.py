@@ -1,0 +1,178 @@
+"""ctypes binding over libpolar.so (include/polar.h).
+
+Argument marshalling only: every step of decoding runs in the library's HIP
+kernels.  Device buffers are torch tensors (memory and streams only).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "libpolar.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, 1, 2, 3, 4
+ALGO = {"fastssc": 0, "sc": 1}
+LLR = {"i8": 0, "f32": 1}
+OP_NAMES = ["F", "G", "G_0R", "Combine", "Combine_0R", "Info", "Repetition", "SPC"]
+EXPORTS = [
+    "polar_construct", "polar_construct_mask", "polar_configure", "polar_prepare", "polar_destroy",
+    "polar_last_status", "polar_strerror", "polar_n", "polar_k", "polar_frozen_mask", "polar_schedule",
+    "polar_encode", "polar_decode", "polar_decode_trace",
+]
+
+
+class PolarError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__("%s: %s" % (what, _lib().polar_strerror(status).decode()))
+
+
+_L = None
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError("libpolar.so is not built (run __graft_entry__.build()); "
+                               "there is no fallback decoder")
+        L = ctypes.CDLL(SO_PATH)
+        P, I = ctypes.c_void_p, ctypes.c_int
+        L.polar_construct.argtypes = [I, I, ctypes.c_double]
+        L.polar_construct.restype = P
+        L.polar_construct_mask.argtypes = [I, P]
+        L.polar_construct_mask.restype = P
+        L.polar_configure.argtypes = [P, I, I]
+        L.polar_prepare.argtypes = [P]
+        L.polar_destroy.argtypes = [P]
+        L.polar_destroy.restype = None
+        L.polar_last_status.argtypes = []
+        L.polar_strerror.argtypes = [I]
+        L.polar_strerror.restype = ctypes.c_char_p
+        L.polar_n.argtypes = [P]
+        L.polar_k.argtypes = [P]
+        L.polar_frozen_mask.argtypes = [P, P]
+        L.polar_schedule.argtypes = [P, P, P, P, I, P]
+        L.polar_encode.argtypes = [P, P, I, P]
+        L.polar_decode.argtypes = [P, P, I, P, P]
+        L.polar_decode_trace.argtypes = [P, P, I, P, P, P]
+        _L = L
+    return _L
+
+
+def lib():
+    return _lib()
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise PolarError(rc, what)
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Code:
+    """A polar code plus its decoder schedule (host) and device tables."""
+
+    def __init__(self, n=None, k=None, design_db=None, algo="fastssc", llr="i8", frozen=None, prepare=True):
+        L = _lib()
+        if frozen is not None:
+            frozen = np.ascontiguousarray(frozen, dtype=np.uint8)
+            h = L.polar_construct_mask(int(frozen.shape[0]), _np_ptr(frozen))
+        else:
+            h = L.polar_construct(int(n), int(k), float(design_db))
+        if not h:
+            raise PolarError(L.polar_last_status(), "polar_construct")
+        self._h = ctypes.c_void_p(h)
+        self.n = L.polar_n(self._h)
+        self.k = L.polar_k(self._h)
+        self.algo, self.llr = algo, llr
+        _check(L.polar_configure(self._h, ALGO[algo], LLR[llr]), "polar_configure")
+        self.prepared = False
+        if prepare:
+            self.prepare()
+
+    def prepare(self):
+        _check(_lib().polar_prepare(self._h), "polar_prepare")
+        self.prepared = True
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().polar_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def row_bytes(self):
+        return (self.k + 7) // 8
+
+    def frozen(self):
+        out = np.zeros(self.n, np.uint8)
+        _check(_lib().polar_frozen_mask(self._h, _np_ptr(out)), "polar_frozen_mask")
+        return out
+
+    def schedule(self):
+        cnt = ctypes.c_int(0)
+        _check(_lib().polar_schedule(self._h, None, None, None, 0, ctypes.byref(cnt)), "polar_schedule")
+        k = np.zeros(cnt.value, np.int32)
+        s = np.zeros(cnt.value, np.int32)
+        o = np.zeros(cnt.value, np.int32)
+        _check(_lib().polar_schedule(self._h, _np_ptr(k), _np_ptr(s), _np_ptr(o), cnt.value, ctypes.byref(cnt)),
+               "polar_schedule")
+        return [(OP_NAMES[a], int(b), int(c)) for a, b, c in zip(k, s, o)]
+
+    def encode(self, info_packed):
+        """Host encoder: [frames, ceil(K/8)] packed info rows -> [frames, ceil(N/8)]."""
+        info = np.ascontiguousarray(np.atleast_2d(info_packed), dtype=np.uint8)
+        x = np.zeros((info.shape[0], (self.n + 7) // 8), np.uint8)
+        _check(_lib().polar_encode(self._h, _np_ptr(info), info.shape[0], _np_ptr(x)), "polar_encode")
+        return x
+
+    def _check_llr(self, llr):
+        import torch
+        want = torch.int8 if self.llr == "i8" else torch.float32
+        if llr.dtype != want or not llr.is_cuda or not llr.is_contiguous() or llr.dim() != 2 or llr.shape[1] != self.n:
+            raise ValueError("llr must be a contiguous CUDA %s tensor [frames, %d]" % (want, self.n))
+
+    def decode(self, llr, out=None, stream=None):
+        """Decode [frames, N] LLRs on the GPU; returns [frames, ceil(K/8)] uint8."""
+        import torch
+        self._check_llr(llr)
+        frames = llr.shape[0]
+        if out is None:
+            out = torch.empty((frames, self.row_bytes), dtype=torch.uint8, device=llr.device)
+        _check(_lib().polar_decode(self._h, ctypes.c_void_p(llr.data_ptr()), frames,
+                                   ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)), "polar_decode")
+        return out
+
+    def decode_trace(self, llr, out=None, trace=None, stream=None):
+        """decode() plus the leaf-LLR trace [frames, N] (LLR dtype)."""
+        import torch
+        self._check_llr(llr)
+        frames = llr.shape[0]
+        if out is None:
+            out = torch.empty((frames, self.row_bytes), dtype=torch.uint8, device=llr.device)
+        if trace is None:
+            trace = torch.zeros_like(llr)
+        _check(_lib().polar_decode_trace(self._h, ctypes.c_void_p(llr.data_ptr()), frames,
+                                         ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(trace.data_ptr()),
+                                         _stream_handle(stream)), "polar_decode_trace")
+        return out, trace

@@ -1,0 +1,99 @@
+"""Host-side logic of libpolar (no GPU needed): exported symbols, argument
+validation, construction, schedule and encoder against the oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1504_00353_amd import binding, synth, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "polar.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(polar_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = binding.lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(binding.EXPORTS)
+
+
+def test_invalid_arguments_are_rejected():
+    L = binding.lib()
+    for n, k in [(0, 0), (3, 1), (6, 3), (65536, 100), (8, 0), (8, 9), (-8, 4)]:
+        assert not L.polar_construct(n, k, 2.0)
+        assert L.polar_last_status() == binding.EINVAL
+    assert not L.polar_construct_mask(8, None)
+    assert L.polar_last_status() == binding.EINVAL
+    allfrozen = np.ones(8, np.uint8)
+    assert not L.polar_construct_mask(8, allfrozen.ctypes.data_as(ctypes.c_void_p))
+    bad = np.array([0, 2, 0, 0], np.uint8)
+    assert not L.polar_construct_mask(4, bad.ctypes.data_as(ctypes.c_void_p))
+    c = binding.Code(64, 32, 2.5, prepare=False)
+    assert L.polar_configure(c.handle, 7, 0) == binding.EINVAL
+    assert L.polar_configure(c.handle, 0, 9) == binding.EINVAL
+    # decode before prepare
+    assert L.polar_decode(c.handle, ctypes.c_void_p(16), 1, ctypes.c_void_p(16), None) == binding.ESTATE
+    assert L.polar_decode(c.handle, None, -1, None, None) == binding.EINVAL
+    assert L.polar_decode(None, None, 1, None, None) == binding.EINVAL
+    assert L.polar_schedule(None, None, None, None, 0, None) == binding.EINVAL
+    assert L.polar_encode(c.handle, None, 1, None) == binding.EINVAL
+    assert L.polar_n(None) == 0 and L.polar_k(None) == 0
+    L.polar_destroy(None)
+    assert binding.lib().polar_strerror(binding.ESTATE) == b"invalid state"
+
+
+CODES = sorted({(n, k, d) for w in workloads.ALL for (n, k, d) in w["codes"]} | {(8, 5, 2.0), (64, 32, 2.5)})
+
+
+@pytest.mark.parametrize("n,k,d", CODES)
+def test_construction_matches_oracle(n, k, d):
+    c = binding.Code(n, k, d, prepare=False)
+    assert c.n == n and c.k == k
+    assert np.array_equal(c.frozen(), oracle.construct(n, k, d))
+
+
+def random_mask(n, rng, p):
+    m = (rng.random(n) < p).astype(np.uint8)
+    if m.all():
+        m[rng.integers(0, n)] = 0
+    return m
+
+
+@pytest.mark.parametrize("algo", ["fastssc", "sc"])
+def test_schedule_matches_oracle_walk(algo):
+    rng = np.random.default_rng(5)
+    masks = [oracle.construct(n, k, d) for (n, k, d) in CODES if n <= 4096 or algo == "fastssc"]
+    masks += [random_mask(n, rng, p) for n in (2, 4, 8, 16, 64, 256, 1024) for p in (0.2, 0.5, 0.8)]
+    for fr in masks:
+        c = binding.Code(frozen=fr, algo=algo, prepare=False)
+        mine = [(name, size) for name, size, _ in c.schedule()]
+        assert mine == oracle.schedule(fr, algo)
+
+
+def test_listing1_schedule_offsets():
+    fr = np.array([1, 1, 0, 0, 1, 0, 0, 0], np.uint8)
+    c = binding.Code(frozen=fr, prepare=False)
+    assert c.schedule() == [("F", 8, 0), ("G_0R", 4, 0), ("Info", 2, 2), ("Combine_0R", 4, 0),
+                            ("G", 8, 0), ("SPC", 4, 4), ("Combine", 8, 0)]
+
+
+@pytest.mark.parametrize("n,k,d", [(8, 5, 2.0), (64, 32, 2.5), (1024, 922, 4.0), (32768, 29492, 4.0)])
+def test_encoder_matches_oracle(n, k, d):
+    c = binding.Code(n, k, d, prepare=False)
+    fr = c.frozen()
+    bits = synth.info_bits(9, np.arange(6), k)
+    x = c.encode(synth.pack_bits(bits))
+    expect = oracle.encode(synth.scatter_info(bits, fr))
+    assert np.array_equal(synth.unpack_bits(x, n), expect)

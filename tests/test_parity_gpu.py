@@ -1,0 +1,186 @@
+"""GPU decode == oracle, element by element.
+
+int8: decoded bits and the leaf-LLR trace are bit-exact against the 8-bit
+saturating oracle.  float32: bits and trace are bit-exact against the
+float32 oracle (same operations in the same order), and the trace is within
+1e-5 of the float64 oracle on the forward-error scale.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from frames import make_frames
+from paper_1504_00353_amd import Code, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def gpu_decode(code, llr, trace=False):
+    t = torch.from_numpy(np.ascontiguousarray(llr)).cuda()
+    if trace:
+        out, tr = code.decode_trace(t)
+        torch.cuda.synchronize()
+        return out.cpu().numpy(), tr.cpu().numpy()
+    out = code.decode(t)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), None
+
+
+def packed_info(frozen, u_hat):
+    return synth.pack_bits(u_hat[:, np.asarray(frozen) == 0])
+
+
+def check_parity(code, frozen, llr, algo, trace=True, label=""):
+    u, _, t = oracle.decode(frozen, llr, algo, trace=trace, nthreads=8)
+    bits, tr = gpu_decode(code, llr, trace=trace)
+    expect = packed_info(frozen, u)
+    bad = np.flatnonzero((bits != expect).any(axis=1))
+    assert bad.size == 0, "%s: %d frames differ, first %s" % (label, bad.size, bad[:5])
+    if trace:
+        diff = np.flatnonzero((tr != t).any(axis=1))
+        assert diff.size == 0, "%s: trace differs in %d frames" % (label, diff.size)
+    return u
+
+
+def random_llrs(rng, frames, n, kind):
+    if kind == "i8":
+        return rng.integers(-128, 128, size=(frames, n)).astype(np.int8)
+    if kind == "i8small":  # many zeros and ties
+        return rng.integers(-3, 4, size=(frames, n)).astype(np.int8)
+    return rng.normal(0.3, 3.0, size=(frames, n)).astype(np.float32)
+
+
+def random_mask(n, rng, p):
+    m = (rng.random(n) < p).astype(np.uint8)
+    if m.all():
+        m[rng.integers(0, n)] = 0
+    return m
+
+
+@pytest.mark.parametrize("algo", ["fastssc", "sc"])
+@pytest.mark.parametrize("kind", ["i8", "i8small", "f32"])
+def test_listing1_code(algo, kind):
+    fr = np.array([1, 1, 0, 0, 1, 0, 0, 0], np.uint8)
+    code = Code(frozen=fr, algo=algo, llr="f32" if kind == "f32" else "i8")
+    rng = np.random.default_rng(1)
+    check_parity(code, fr, random_llrs(rng, 333, 8, kind), algo, label="listing1")
+
+
+@pytest.mark.parametrize("n", [2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 8192])
+@pytest.mark.parametrize("algo", ["fastssc", "sc"])
+@pytest.mark.parametrize("kind", ["i8", "i8small", "f32"])
+def test_random_masks(n, algo, kind):
+    """Arbitrary frozen sets exercise every node kind, including a Rate-0
+    right child under a non-frozen left child."""
+    if algo == "sc" and n > 2048:
+        pytest.skip("plain SC covered up to N = 2048 here")
+    rng = np.random.default_rng(n * 7 + len(kind) + (3 if algo == "sc" else 0))
+    for p in (0.1, 0.5, 0.9):
+        fr = random_mask(n, rng, p)
+        code = Code(frozen=fr, algo=algo, llr="f32" if kind == "f32" else "i8")
+        check_parity(code, fr, random_llrs(rng, 67, n, kind), algo, label="mask n=%d p=%.1f" % (n, p))
+
+
+CODES = [(64, 32, 2.5), (256, 128, 2.5), (256, 230, 4.0), (1024, 512, 2.5), (1024, 922, 4.0),
+         (4096, 3400, 4.0), (4096, 3686, 4.0), (16384, 14746, 4.0), (32768, 27197, 4.0), (32768, 29492, 4.0)]
+
+
+@pytest.mark.parametrize("n,k,d", CODES)
+@pytest.mark.parametrize("llr", ["i8", "f32"])
+def test_constructed_codes_channel_frames(n, k, d, llr):
+    code = Code(n, k, d, llr=llr)
+    fr = code.frozen()
+    frames = 130 if n <= 4096 else 40
+    _, _, l = make_frames(fr, 77, frames, d - 0.5, llr)
+    check_parity(code, fr, l, "fastssc", label="(%d,%d) %s" % (n, k, llr))
+
+
+def test_sc_1024_512_float32_full_workload():
+    """(1024,512), plain SC, float32, 10,000 frames at 2.5 dB."""
+    code = Code(1024, 512, 2.5, algo="sc", llr="f32")
+    fr = code.frozen()
+    _, _, l = make_frames(fr, 1, 10000, 2.5, "f32")
+    check_parity(code, fr, l, "sc", label="sc-1024")
+    # float32 trace against float64: within 1e-5 of the forward-error scale
+    sub = l[:200]
+    _, tr = gpu_decode(code, sub, trace=True)
+    _, _, t64 = oracle.decode(fr, sub.astype(np.float64), "sc", trace=True, nthreads=8)
+    scale = np.abs(sub.astype(np.float64)).max(axis=1, keepdims=True) * 1024
+    assert (np.abs(tr.astype(np.float64) - t64) <= 1e-5 * scale).all()
+
+
+@pytest.mark.parametrize("llr", ["i8", "f32"])
+def test_fastssc_32768_29492_full_workload(llr):
+    """(32768,29492) Fast-SSC, 4,096 frames at 4.0 dB, every frame."""
+    code = Code(32768, 29492, 4.0, llr=llr)
+    fr = code.frozen()
+    _, _, l = make_frames(fr, 2, 4096, 4.0, llr)
+    check_parity(code, fr, l, "fastssc", trace=True, label="32k " + llr)
+
+
+@pytest.mark.parametrize("n,k", [(4096, 3686), (32768, 29492)])
+def test_stress_launch_262144_frames_sampled(n, k):
+    """One launch of 262,144 frames (a pool of 2,048 distinct frames tiled);
+    sampled frames against the oracle, and every tile identical."""
+    code = Code(n, k, 4.0, llr="i8")
+    fr = code.frozen()
+    pool = 2048
+    _, _, l = make_frames(fr, 5, pool, 4.5, "i8")
+    u, _, _ = oracle.decode(fr, l, "fastssc", nthreads=8)
+    expect = packed_info(fr, u)
+    frames = 262144
+    dev = torch.from_numpy(l).cuda().repeat(frames // pool, 1)
+    out = code.decode(dev)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    rng = np.random.default_rng(0)
+    idx = rng.choice(frames, size=4096, replace=False)
+    assert np.array_equal(out[idx], expect[idx % pool])
+    assert (out.reshape(frames // pool, pool, -1) == expect[None]).all()
+
+
+@pytest.mark.parametrize("n,k", [(64, 64), (4096, 4096), (64, 1), (32768, 1), (64, 63), (8192, 8191), (2, 1), (2, 2)])
+@pytest.mark.parametrize("kind", ["i8", "f32"])
+def test_degenerate_codes(n, k, kind):
+    """Root is a Rate-1, repetition or SPC node; N = 2."""
+    code = Code(n, k, 3.0, llr="f32" if kind == "f32" else "i8")
+    fr = code.frozen()
+    rng = np.random.default_rng(n + k)
+    check_parity(code, fr, random_llrs(rng, 65, n, kind), "fastssc", label="(%d,%d)" % (n, k))
+
+
+def test_extreme_and_zero_llrs():
+    code = Code(1024, 922, 4.0, llr="i8")
+    fr = code.frozen()
+    rng = np.random.default_rng(3)
+    l = np.zeros((8, 1024), np.int8)
+    l[1] = 127
+    l[2] = -128
+    l[3] = -127
+    l[4] = rng.choice([-128, 127], size=1024)
+    l[5] = rng.choice([-128, 0, 127], size=1024)
+    l[6] = rng.choice([-1, 0, 1], size=1024)
+    l[7] = rng.integers(-128, 128, size=1024)
+    check_parity(code, fr, l, "fastssc", label="extremes")
+
+
+def test_noiseless_recovery_on_gpu():
+    for (n, k, d) in [(1024, 512, 2.5), (32768, 29492, 4.0)]:
+        for llr in ("i8", "f32"):
+            code = Code(n, k, d, llr=llr)
+            fr = code.frozen()
+            bits = synth.info_bits(8, np.arange(16), k)
+            x = oracle.encode(synth.scatter_info(bits, fr))
+            sign = 1 - 2 * x.astype(np.int32)
+            l = (sign * 31).astype(np.int8) if llr == "i8" else (sign * 8.0).astype(np.float32)
+            out, _ = gpu_decode(code, l)
+            assert np.array_equal(out, synth.pack_bits(bits))
+
+
+def test_zero_frames_is_noop():
+    code = Code(256, 128, 2.5)
+    t = torch.zeros((0, 256), dtype=torch.int8, device="cuda")
+    out = code.decode(t)
+    torch.cuda.synchronize()
+    assert out.shape == (0, 16)
