@@ -10,6 +10,7 @@ SOURCES = ["decode.hip", "api.cpp", "construct.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-fno-honor-nans", "-fno-honor-infinities", "-ffp-contract=off",
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

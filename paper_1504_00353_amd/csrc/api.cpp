@@ -13,7 +13,7 @@ namespace polar {
 int wave_lds_bytes(int log2n, int k, int llr_type);
 int launch_decode(const uint32_t* ops, int nops, int log2n, int kbits, int llr_type, const void* llr, int nframes,
                   uint8_t* bits, void* trace, int waves_per_block, void* stream);
-int set_lds_limit(int llr_type, int bytes);
+int set_lds_limit(int llr_type, int log2n, int bytes);
 }  // namespace polar
 
 struct polar_code {
@@ -132,7 +132,7 @@ polar_status polar_prepare(polar_code* c) {
   int wpb = lds_max / wave_bytes;
   if (wpb > 4) wpb = 4;
   if (wpb < 1) wpb = 1;
-  if (polar::set_lds_limit(c->llr_type, wpb * wave_bytes) != hipSuccess) return set(POLAR_EDEVICE);
+  if (polar::set_lds_limit(c->llr_type, c->plan.log2n, wpb * wave_bytes) != hipSuccess) return set(POLAR_EDEVICE);
   const size_t bytes = c->plan.dops.size() * sizeof(uint32_t);
   uint32_t* d = nullptr;
   if (hipMalloc((void**)&d, bytes ? bytes : 4) != hipSuccess) return set(POLAR_ENOMEM);
@@ -141,7 +141,7 @@ polar_status polar_prepare(polar_code* c) {
     return set(POLAR_EDEVICE);
   }
   c->d_ops = d;
-  c->nops = (int)(c->plan.dops.size() / 2);
+  c->nops = c->plan.nops;
   c->device = dev;
   c->waves_per_block = wpb;
   c->prepared = true;

@@ -14,6 +14,7 @@
 // decoder tree.  Fast-SSC stops at Rate-0, Rate-1, repetition and SPC nodes;
 // plain SC decides single bits and only skips all-frozen sub-trees (their
 // estimate is zero whatever the LLRs, so the decoded bits are unchanged).
+// The device form is one 32-bit op per step of that walk.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -86,11 +87,6 @@ struct Walker {
     p.loff.push_back(o);
   }
 
-  void dev(DeviceOp op, int stage, int o, int out = 0) {
-    p.dops.push_back(pack_op(op, stage, o));
-    p.dops.push_back((uint32_t)out);
-  }
-
   void logical(int o, int stage) {
     const int size = 1 << stage;
     switch (logical_kind(o, size)) {
@@ -115,16 +111,18 @@ struct Walker {
     }
   }
 
-  // needed: some later G or combine reads this node's beta.
+  void dev(DeviceOp op, int stage, int o) { p.dops.push_back(pack_op(op, stage, o)); }
+
+  // needed: some later G or combine reads this node's beta (the estimate of
+  // the root and of the nodes on its right spine is never read).
   void device(int o, int stage, bool needed) {
     const int size = 1 << stage;
     const NodeKind kind = device_kind(o, size);
-    const int out = info_before[o];
     switch (kind) {
       case N_RATE0: return;
-      case N_RATE1: dev(DOP_R1, stage, o, out); break;
-      case N_REP: dev(DOP_REP, stage, o, out + 0); break;
-      case N_SPC: dev(DOP_SPC, stage, o, out); break;
+      case N_RATE1: dev(DOP_R1, stage, o); break;
+      case N_REP: dev(DOP_REP, stage, o); break;
+      case N_SPC: dev(DOP_SPC, stage, o); break;
       case N_INTERNAL: {
         const int h = size / 2;
         const bool left_rate0 = frozen_count(o, h) == h;
@@ -162,6 +160,8 @@ void build_schedule(Plan& plan) {
   Walker w(plan);
   w.logical(0, plan.log2n);
   w.device(0, plan.log2n, false);
+  plan.nops = (int)plan.dops.size();
+  plan.dops.push_back(pack_op(DOP_END, 0, 0));  // the kernel prefetches one op ahead
 }
 
 }  // namespace polar

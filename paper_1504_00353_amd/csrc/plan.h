@@ -21,12 +21,12 @@ enum LogicalOp : int32_t {
   LOP_CR0 = 8,    // combine with a Rate-0 right child (arbitrary masks only)
 };
 
-// Device op codes.  One op is two 32-bit words:
-//   w0 = code | stage << 8 | node_offset << 16      (node_offset < 2^16)
-//   w1 = bit offset of the node's first information bit in the output row
+// Device op codes.  One op is one 32-bit word:
+//   code | stage << 8 | node_offset << 16      (node_offset < 2^16)
 // "stage" is log2 of the node size Nv; F/G/G0R read stage k and write
-// stage k-1.  Stages <= 6 live in VGPRs (one element per lane), larger
-// stages in LDS; stage log2(N) is the channel frame in global memory.
+// stage k-1; leaves and combines act on a node of stage k.  Decision nodes
+// append their information bits to the output in schedule order, which is
+// increasing index order.
 enum DeviceOp : uint32_t {
   DOP_F = 0,
   DOP_G = 1,
@@ -38,6 +38,7 @@ enum DeviceOp : uint32_t {
   DOP_REP = 7,
   DOP_SPC = 8,
   DOP_FLUSH = 9,  // write the 64-bit beta window of a finished size-64 node to LDS
+  DOP_END = 10,   // padding after the last op
 };
 
 constexpr int kRegStages = 6;       // stages 0..6 (sizes 1..64) are register resident
@@ -55,7 +56,8 @@ struct Plan {
   int algo = 0;     // 0 Fast-SSC, 1 SC
   std::vector<uint8_t> frozen;          // N flags
   std::vector<int32_t> lkind, lsize, loff;  // logical schedule
-  std::vector<uint32_t> dops;           // device schedule, 2 words per op
+  std::vector<uint32_t> dops;           // device schedule, one word per op, plus one padding op
+  int nops = 0;
 };
 
 // Builds the logical and device schedules for plan.frozen / plan.algo.
