@@ -13,6 +13,7 @@ Gb/s single-core figure for this code.  Prints one JSON line:
   cpu_baseline the CPU oracle on a bounded sample on this host's cores.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -36,6 +37,56 @@ def make_inputs(code, seed, frames, ebn0_db):
     z = synth.noise(seed, idx, code.n)
     llr = synth.quantize6(synth.awgn_llr(x, z, ebn0_db, code.k / code.n))
     return fr, bits, llr
+
+
+def kernel_source_hash():
+    """Hash of the sources that make up the decode kernel; HBM counter
+    readings are only valid for the kernel they were taken on."""
+    h = hashlib.sha256()
+    for f in ("decode.hip", "plan.h", "construct.cpp"):
+        with open(os.path.join(ROOT, "paper_1504_00353_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+PMC_FILE = os.path.join(ROOT, "profiles", "decode_kernel_i8_32768x29492_hbm_traffic.txt")
+
+
+def measured_traffic(frames):
+    """HBM bytes per launch from the committed counter summary: FETCH_SIZE
+    and WRITE_SIZE of the decode kernel, each scaled by the same counter's
+    reading on a plain copy of known size.  None when there is no summary
+    for this frame count or the kernel sources changed since it was taken."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    kv = {}
+    with open(PMC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                a, b = line.split(":", 1)
+                kv[a.strip()] = b.strip()
+    try:
+        if kv.get("kernel_source_hash") != kernel_source_hash() or int(kv["frames"]) != frames:
+            return None
+        copy_bytes = float(kv["copy_bytes"])
+        fetch = float(kv["decode_fetch_kib"]) * copy_bytes / float(kv["copy_fetch_kib"])
+        write = float(kv["decode_write_kib"]) * copy_bytes / float(kv["copy_write_kib"])
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+    return fetch + write
+
+
+def copy_calibration(nbytes, reps):
+    """A plain copy of known size (read nbytes, write nbytes) for scaling
+    the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.randint(-128, 127, (nbytes,), dtype=torch.int8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        torch.bitwise_not(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "reps": reps,
+                      "kernel": "elementwise bitwise_not int8 (reads and writes each byte once)"}), flush=True)
 
 
 def percentile(v, p):
@@ -71,6 +122,8 @@ def main():
     ap.add_argument("--latency-runs", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -78,6 +131,10 @@ def main():
               "each run this same single-GPU decode on their own share (no collectives); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, max(args.steps, 1))
+        return
 
     import torch
     from paper_1504_00353_amd import Code, synth
@@ -125,28 +182,34 @@ def main():
 
     # plain: one launch per frame, back to back, same frames
     pf = min(args.plain_frames, frames)
-    outs1 = torch.empty((pf, code.row_bytes), dtype=torch.uint8, device=dev)
-    for i in range(3):
-        code.decode(llr[i:i + 1], out=outs1[i:i + 1])
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    for i in range(pf):
-        code.decode(llr[i:i + 1], out=outs1[i:i + 1])
-    torch.cuda.synchronize()
-    plain_wall = time.perf_counter() - t
-    plain_gbps = float(k) * pf / plain_wall / 1e9
-    assert torch.equal(outs1, out[:pf]), "plain and batched decodes differ"
-    plat = []
-    for i in range(min(pf, 100)):
+    plain = None
+    if pf > 0:
+        outs1 = torch.empty((pf, code.row_bytes), dtype=torch.uint8, device=dev)
+        for i in range(min(3, pf)):
+            code.decode(llr[i:i + 1], out=outs1[i:i + 1])
         torch.cuda.synchronize()
         t = time.perf_counter()
-        code.decode(llr[i:i + 1], out=outs1[i:i + 1])
+        for i in range(pf):
+            code.decode(llr[i:i + 1], out=outs1[i:i + 1])
         torch.cuda.synchronize()
-        plat.append((time.perf_counter() - t) * 1e6)
+        plain_wall = time.perf_counter() - t
+        plain_gbps = float(k) * pf / plain_wall / 1e9
+        assert torch.equal(outs1, out[:pf]), "plain and batched decodes differ"
+        plat = []
+        for i in range(min(pf, 100)):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            code.decode(llr[i:i + 1], out=outs1[i:i + 1])
+            torch.cuda.synchronize()
+            plat.append((time.perf_counter() - t) * 1e6)
+        plain = {"value": round(plain_gbps, 4), "unit": "Gbps", "frames": pf,
+                 "latency_us": {"p50": round(percentile(plat, 50), 2), "p99": round(percentile(plat, 99), 2)},
+                 "bits_equal_batched": True}
 
     bytes_per_frame = n * 1 + (k + 7) // 8
     mean_kernel_s = float(np.mean(kernel_ms)) / 1e3
     achieved = bytes_per_frame * frames / mean_kernel_s / 1e9
+    traffic = measured_traffic(frames)
 
     result = {
         "metric": METRIC,
@@ -163,14 +226,14 @@ def main():
         "data": "synthetic: uniform info bits, BPSK over AWGN at 4.0 dB, 6-bit LLRs in int8",
         "config": {"workload": "fastssc_32768_29492_i8", "N": n, "K": k, "design_ebn0_db": design,
                    "ebn0_db": ebn0, "frames_per_step": frames, "algo": "fast-ssc"},
-        "latency_us": {"p50": round(percentile(lat, 50), 2), "p99": round(percentile(lat, 99), 2),
-                       "what": "batched launch of %d frames, submit to completion" % frames},
-        "plain": {"value": round(plain_gbps, 4), "unit": "Gbps", "frames": pf,
-                  "latency_us": {"p50": round(percentile(plat, 50), 2), "p99": round(percentile(plat, 99), 2)},
-                  "bits_equal_batched": True},
+        "latency_us": None if not lat else
+        {"p50": round(percentile(lat, 50), 2), "p99": round(percentile(lat, 99), 2),
+         "what": "batched launch of %d frames, submit to completion" % frames},
+        "plain": plain,
         "fer": fer,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": None if traffic is None else round(traffic),
                      "kernel": "decode_kernel<int8>", "bytes_per_frame": bytes_per_frame,
                      "mean_kernel_ms": round(mean_kernel_s * 1e3, 4)},
     }

@@ -780,13 +780,23 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint32_t* __restrict_
   }
   wave_sync();
 
-  uint32_t next = ops[0];
-  for (int pc = 0; pc < nops; ++pc) {
-    const uint32_t w0 = rfl(next);
-    next = ops[pc + 1];  // the schedule carries one padding op
-    d.op(w0);
-    d.settle();
-    wave_sync();
+  // The schedule is read 64 ops at a time, one op per lane, with the next
+  // block in flight; each op is taken out of the block with readlane.  The
+  // block is moved into place by an opaque copy at the block boundary, so
+  // the wait for its load happens there and not at every op.
+  const __amdgpu_buffer_rsrc_t opr = __builtin_amdgcn_make_buffer_rsrc((void*)ops, 0, nops * 4, 0x00020000);
+  uint32_t nxt = __builtin_amdgcn_raw_buffer_load_b32(opr, 4 * lane, 0, 0);
+  for (int pb = 0; pb < nops; pb += 64) {
+    uint32_t blk;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(blk) : "v"(nxt));
+    nxt = __builtin_amdgcn_raw_buffer_load_b32(opr, 4 * (pb + 64 + lane), 0, 0);
+    const int cnt = (int)rfl((uint32_t)min(64, nops - pb));
+    for (int j = 0; j < cnt; ++j) {
+      const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)blk, j);
+      d.op(w0);
+      d.settle();
+      wave_sync();
+    }
   }
   if (d.fill > 0) d.emit(d.acc);
 }
