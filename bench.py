@@ -43,24 +43,27 @@ def kernel_source_hash():
     """Hash of the sources that make up the decode kernel; HBM counter
     readings are only valid for the kernel they were taken on."""
     h = hashlib.sha256()
-    for f in ("decode.hip", "plan.h", "construct.cpp"):
+    for f in ("decode_ops.h", "opcodes.h", "decode.hip", "unrolled.cpp", "plan.h", "construct.cpp"):
         with open(os.path.join(ROOT, "paper_1504_00353_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-PMC_FILE = os.path.join(ROOT, "profiles", "decode_kernel_i8_32768x29492_hbm_traffic.txt")
+def pmc_file(kernel):
+    name = "polar_unrolled" if kernel == "unrolled" else "decode_kernel"
+    return os.path.join(ROOT, "profiles", "%s_i8_32768x29492_hbm_traffic.txt" % name)
 
 
-def measured_traffic(frames):
+def measured_traffic(frames, kernel):
     """HBM bytes per launch from the committed counter summary: FETCH_SIZE
     and WRITE_SIZE of the decode kernel, each scaled by the same counter's
     reading on a plain copy of known size.  None when there is no summary
     for this frame count or the kernel sources changed since it was taken."""
-    if not os.path.exists(PMC_FILE):
+    path = pmc_file(kernel)
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(PMC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith(" "):
                 a, b = line.split(":", 1)
@@ -122,6 +125,8 @@ def main():
     ap.add_argument("--latency-runs", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--kernel", choices=["unrolled", "schedule"], default="unrolled",
+                    help="generated per-code kernel (default) or the schedule-interpreting one")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -141,7 +146,7 @@ def main():
 
     n, k, design, ebn0 = 32768, 29492, 4.0, 4.0
     frames = args.frames
-    code = Code(n, k, design, algo="fastssc", llr="i8")
+    code = Code(n, k, design, algo="fastssc", llr="i8", kernel=args.kernel)
     frozen, info, llr_np = make_inputs(code, seed=2, frames=frames, ebn0_db=ebn0)
     dev = torch.device("cuda", 0)
     llr = torch.from_numpy(llr_np).to(dev)
@@ -209,7 +214,7 @@ def main():
     bytes_per_frame = n * 1 + (k + 7) // 8
     mean_kernel_s = float(np.mean(kernel_ms)) / 1e3
     achieved = bytes_per_frame * frames / mean_kernel_s / 1e9
-    traffic = measured_traffic(frames)
+    traffic = measured_traffic(frames, args.kernel)
 
     result = {
         "metric": METRIC,
@@ -225,7 +230,8 @@ def main():
         "dtype": "i8",
         "data": "synthetic: uniform info bits, BPSK over AWGN at 4.0 dB, 6-bit LLRs in int8",
         "config": {"workload": "fastssc_32768_29492_i8", "N": n, "K": k, "design_ebn0_db": design,
-                   "ebn0_db": ebn0, "frames_per_step": frames, "algo": "fast-ssc"},
+                   "ebn0_db": ebn0, "frames_per_step": frames, "algo": "fast-ssc",
+                   "kernel": args.kernel},
         "latency_us": None if not lat else
         {"p50": round(percentile(lat, 50), 2), "p99": round(percentile(lat, 99), 2),
          "what": "batched launch of %d frames, submit to completion" % frames},
@@ -234,7 +240,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": None if traffic is None else round(traffic),
-                     "kernel": "decode_kernel<int8>", "bytes_per_frame": bytes_per_frame,
+                     "kernel": "polar_unrolled (int8)" if args.kernel == "unrolled" else "decode_kernel<int8>",
+                     "bytes_per_frame": bytes_per_frame,
                      "mean_kernel_ms": round(mean_kernel_s * 1e3, 4)},
     }
     if not args.no_cpu:

@@ -39,12 +39,26 @@ typedef enum {
   POLAR_ENOMEM = 2,  /* host or device allocation failed, or the code needs
                         more on-chip memory than the device offers */
   POLAR_EDEVICE = 3, /* a HIP call failed (launch error, no device) */
-  POLAR_ESTATE = 4   /* call out of order: e.g. decode before prepare,
+  POLAR_ESTATE = 4,  /* call out of order: e.g. decode before prepare,
                         configure after prepare */
+  POLAR_ECOMPILE = 5 /* the code's unrolled kernel failed to compile */
 } polar_status;
 
 typedef enum { POLAR_ALGO_FASTSSC = 0, POLAR_ALGO_SC = 1 } polar_algo;
 typedef enum { POLAR_LLR_I8 = 0, POLAR_LLR_F32 = 1 } polar_llr;
+
+/* Which kernel decodes a code (Sec. III-A vs III-B: instruction-based vs
+ * unrolled decoder).  Both run the same node functions on the same data
+ * layout and give identical results.
+ *   POLAR_KERNEL_SCHEDULE: one kernel for every code reads the code's
+ *     schedule from device memory at run time; prepare is immediate.
+ *   POLAR_KERNEL_UNROLLED: a kernel generated for this one code, with the
+ *     schedule compiled in (no run-time dispatch).  It is compiled with the
+ *     HIP run-time compiler the first time a code needs it (seconds to a
+ *     minute for N = 32768) and kept in an on-disk cache: the directory in
+ *     the environment variable POLAR_KERNEL_CACHE, else "kernels" next to
+ *     the library file. */
+typedef enum { POLAR_KERNEL_SCHEDULE = 0, POLAR_KERNEL_UNROLLED = 1 } polar_kernel;
 
 /* Node functions reported by polar_schedule(), named after Listing 1. */
 typedef enum {
@@ -77,11 +91,22 @@ polar_code* polar_construct_mask(int n, const uint8_t* frozen);
  * called before polar_prepare(); POLAR_ESTATE afterwards. */
 polar_status polar_configure(polar_code* code, int algo, int llr_type);
 
-/* Uploads the schedule to the current HIP device and sizes the launch for
- * it.  Synchronous; allocates device memory; call it before any capture.
+/* Selects the kernel (polar_kernel); default POLAR_KERNEL_SCHEDULE.  Must
+ * be called before polar_prepare(); POLAR_ESTATE afterwards. */
+polar_status polar_set_kernel(polar_code* code, int kernel);
+
+/* Generates and compiles the unrolled kernel of the code as configured
+ * (algorithm and LLR type) into the kernel cache, unless it is there
+ * already.  Host only: needs no device, so kernels can be built ahead of
+ * time.  Synchronous.  Errors: POLAR_ECOMPILE, POLAR_ENOMEM. */
+polar_status polar_build_kernel(const polar_code* code);
+
+/* Uploads the schedule (or loads the unrolled kernel, building it first if
+ * the cache lacks it) on the current HIP device and sizes the launch.
+ * Synchronous; allocates device memory; call it before any capture.
  * Errors: POLAR_EDEVICE (no device / HIP failure), POLAR_ENOMEM (device
  * allocation, or the decoder's on-chip working set does not fit the
- * device's LDS), POLAR_ESTATE (already prepared). */
+ * device's LDS), POLAR_ECOMPILE, POLAR_ESTATE (already prepared). */
 polar_status polar_prepare(polar_code* code);
 
 /* Frees host and device memory of the code.  NULL is a no-op.  The caller

@@ -11,14 +11,15 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(_HERE, "libpolar.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ESTATE = 0, 1, 2, 3, 4
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ECOMPILE = 0, 1, 2, 3, 4, 5
 ALGO = {"fastssc": 0, "sc": 1}
 LLR = {"i8": 0, "f32": 1}
+KERNEL = {"schedule": 0, "unrolled": 1}
 OP_NAMES = ["F", "G", "G_0R", "Combine", "Combine_0R", "Info", "Repetition", "SPC"]
 EXPORTS = [
     "polar_construct", "polar_construct_mask", "polar_configure", "polar_prepare", "polar_destroy",
     "polar_last_status", "polar_strerror", "polar_n", "polar_k", "polar_frozen_mask", "polar_schedule",
-    "polar_encode", "polar_decode", "polar_decode_trace",
+    "polar_encode", "polar_decode", "polar_decode_trace", "polar_set_kernel", "polar_build_kernel",
 ]
 
 
@@ -45,6 +46,8 @@ def _lib():
         L.polar_construct_mask.restype = P
         L.polar_configure.argtypes = [P, I, I]
         L.polar_prepare.argtypes = [P]
+        L.polar_set_kernel.argtypes = [P, I]
+        L.polar_build_kernel.argtypes = [P]
         L.polar_destroy.argtypes = [P]
         L.polar_destroy.restype = None
         L.polar_last_status.argtypes = []
@@ -83,7 +86,8 @@ def _stream_handle(stream):
 class Code:
     """A polar code plus its decoder schedule (host) and device tables."""
 
-    def __init__(self, n=None, k=None, design_db=None, algo="fastssc", llr="i8", frozen=None, prepare=True):
+    def __init__(self, n=None, k=None, design_db=None, algo="fastssc", llr="i8", frozen=None, prepare=True,
+                 kernel="schedule"):
         L = _lib()
         if frozen is not None:
             frozen = np.ascontiguousarray(frozen, dtype=np.uint8)
@@ -97,6 +101,8 @@ class Code:
         self.k = L.polar_k(self._h)
         self.algo, self.llr = algo, llr
         _check(L.polar_configure(self._h, ALGO[algo], LLR[llr]), "polar_configure")
+        self.kernel = kernel
+        _check(L.polar_set_kernel(self._h, KERNEL[kernel]), "polar_set_kernel")
         self.prepared = False
         if prepare:
             self.prepare()
@@ -104,6 +110,10 @@ class Code:
     def prepare(self):
         _check(_lib().polar_prepare(self._h), "polar_prepare")
         self.prepared = True
+
+    def build_kernel(self):
+        """Compile this code's unrolled kernel into the kernel cache (host only)."""
+        _check(_lib().polar_build_kernel(self._h), "polar_build_kernel")
 
     def close(self):
         if getattr(self, "_h", None):

@@ -3,27 +3,30 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstring>
+#include <string>
 #include <new>
 #include <vector>
 
 #include "../../include/polar.h"
 #include "plan.h"
+#include "unrolled.h"
 
 namespace polar {
-int wave_lds_bytes(int log2n, int k, int llr_type);
 int launch_decode(const uint32_t* ops, int nops, int log2n, int kbits, int llr_type, const void* llr, int nframes,
                   uint8_t* bits, void* trace, int waves_per_block, void* stream);
-int set_lds_limit(int llr_type, int log2n, int bytes);
+int set_lds_limit(int llr_type, int bytes);
 }  // namespace polar
 
 struct polar_code {
   polar::Plan plan;
   int llr_type = POLAR_LLR_I8;
+  int kernel = POLAR_KERNEL_SCHEDULE;
   bool prepared = false;
   int device = -1;
   uint32_t* d_ops = nullptr;
   int nops = 0;
   int waves_per_block = 1;
+  polar::UnrolledKernel unrolled;
 };
 
 namespace {
@@ -119,6 +122,26 @@ polar_status polar_configure(polar_code* c, int algo, int llr_type) {
   return set(POLAR_OK);
 }
 
+polar_status polar_set_kernel(polar_code* c, int kernel) {
+  if (!c) return set(POLAR_EINVAL);
+  if (c->prepared) return set(POLAR_ESTATE);
+  if (kernel != POLAR_KERNEL_SCHEDULE && kernel != POLAR_KERNEL_UNROLLED) return set(POLAR_EINVAL);
+  c->kernel = kernel;
+  return set(POLAR_OK);
+}
+
+polar_status polar_build_kernel(const polar_code* c) {
+  if (!c) return set(POLAR_EINVAL);
+  try {
+    std::vector<char> code;
+    std::string log;
+    if (polar::unrolled_code_object(c->plan, c->llr_type, code, log) != 0) return set(POLAR_ECOMPILE);
+  } catch (const std::bad_alloc&) {
+    return set(POLAR_ENOMEM);
+  }
+  return set(POLAR_OK);
+}
+
 polar_status polar_prepare(polar_code* c) {
   if (!c) return set(POLAR_EINVAL);
   if (c->prepared) return set(POLAR_ESTATE);
@@ -127,21 +150,32 @@ polar_status polar_prepare(polar_code* c) {
   int lds_max = 0;
   if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return set(POLAR_EDEVICE);
-  const int wave_bytes = polar::wave_lds_bytes(c->plan.log2n, c->plan.k, c->llr_type);
+  const int wave_bytes = polar::wave_lds_bytes(c->plan.log2n, c->llr_type == POLAR_LLR_F32 ? 4 : 1);
   if (wave_bytes > lds_max) return set(POLAR_ENOMEM);
   int wpb = lds_max / wave_bytes;
   if (wpb > 4) wpb = 4;
   if (wpb < 1) wpb = 1;
-  if (polar::set_lds_limit(c->llr_type, c->plan.log2n, wpb * wave_bytes) != hipSuccess) return set(POLAR_EDEVICE);
-  const size_t bytes = c->plan.dops.size() * sizeof(uint32_t);
-  uint32_t* d = nullptr;
-  if (hipMalloc((void**)&d, bytes ? bytes : 4) != hipSuccess) return set(POLAR_ENOMEM);
-  if (bytes && hipMemcpy(d, c->plan.dops.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(d);
-    return set(POLAR_EDEVICE);
+  if (c->kernel == POLAR_KERNEL_UNROLLED) {
+    try {
+      std::vector<char> code;
+      std::string log;
+      if (polar::unrolled_code_object(c->plan, c->llr_type, code, log) != 0) return set(POLAR_ECOMPILE);
+      if (polar::unrolled_load(code, c->unrolled) != 0) return set(POLAR_EDEVICE);
+    } catch (const std::bad_alloc&) {
+      return set(POLAR_ENOMEM);
+    }
+  } else {
+    if (polar::set_lds_limit(c->llr_type, wpb * wave_bytes) != hipSuccess) return set(POLAR_EDEVICE);
+    const size_t bytes = c->plan.dops.size() * sizeof(uint32_t);
+    uint32_t* d = nullptr;
+    if (hipMalloc((void**)&d, bytes ? bytes : 4) != hipSuccess) return set(POLAR_ENOMEM);
+    if (bytes && hipMemcpy(d, c->plan.dops.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(d);
+      return set(POLAR_EDEVICE);
+    }
+    c->d_ops = d;
+    c->nops = c->plan.nops;
   }
-  c->d_ops = d;
-  c->nops = c->plan.nops;
   c->device = dev;
   c->waves_per_block = wpb;
   c->prepared = true;
@@ -150,11 +184,12 @@ polar_status polar_prepare(polar_code* c) {
 
 void polar_destroy(polar_code* c) {
   if (!c) return;
-  if (c->d_ops) {
+  if (c->d_ops || c->unrolled.module) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     if (cur != c->device) (void)hipSetDevice(c->device);
-    (void)hipFree(c->d_ops);
+    if (c->d_ops) (void)hipFree(c->d_ops);
+    polar::unrolled_unload(c->unrolled);
     if (cur != c->device) (void)hipSetDevice(cur);
   }
   delete c;
@@ -169,6 +204,7 @@ const char* polar_strerror(polar_status s) {
     case POLAR_ENOMEM: return "out of memory";
     case POLAR_EDEVICE: return "device error";
     case POLAR_ESTATE: return "invalid state";
+    case POLAR_ECOMPILE: return "kernel compilation failed";
   }
   return "unknown status";
 }
@@ -232,8 +268,11 @@ static polar_status decode_impl(const polar_code* c, const void* llr, int nframe
   if (!llr || !bits) return set(POLAR_EINVAL);
   if (((uintptr_t)llr & 3u) != 0) return set(POLAR_EINVAL);
   if (c->llr_type == POLAR_LLR_F32 && trace && ((uintptr_t)trace & 3u) != 0) return set(POLAR_EINVAL);
-  const int rc = polar::launch_decode(c->d_ops, c->nops, c->plan.log2n, c->plan.k, c->llr_type, llr, nframes, bits,
-                                      trace, c->waves_per_block, stream);
+  const int rc = c->kernel == POLAR_KERNEL_UNROLLED
+                     ? polar::unrolled_launch(c->unrolled, c->plan.log2n, c->llr_type, llr, nframes, bits, trace,
+                                              c->waves_per_block, stream)
+                     : polar::launch_decode(c->d_ops, c->nops, c->plan.log2n, c->plan.k, c->llr_type, llr, nframes,
+                                            bits, trace, c->waves_per_block, stream);
   return set(rc == 0 ? POLAR_OK : POLAR_EDEVICE);
 }
 

@@ -1,723 +1,10 @@
-// Fast-SSC / SC polar decoding kernels for gfx950 (MI355X).
-//
-// One wavefront decodes one frame by interpreting the device schedule built
-// on the host: the ops of a depth-first pre-order walk of the pruned decoder
-// tree (the form of Listing 1).  The schedule is the same for every frame of
-// a code, so every branch of the interpreter is wave-uniform.
-//
-// Where the LLR messages alpha live (one buffer per stage, Sec. III-B.3):
-//   stages 0..6  (node sizes 1..64): one element per lane, f32 VGPRs.  f and
-//                g fetch the partner element i + N_v/2 with DPP row shifts
-//                or the gfx950 permlane16/32 swaps;
-//   stages 7..   LDS, natural order, int8 (int8 codes) or f32.  A lane works
-//                on 16 contiguous bytes (or 4 for small nodes), so the pair
-//                i, i + N_v/2 of f and g is lane-local; int8 values are
-//                computed as packed 16-bit integers scaled by 256;
-//   stage log2N  the channel frame, read with bounds-checked buffer loads.
-// Bit estimates beta use one in-place N-bit array (Sec. III-B.2): nodes of
-// size <= 64 keep their 64-bit block in a wave-uniform register (combines
-// are scalar ALU work, g turns the bits into a lane predicate); a finished
-// size-64 node flushes it to the LDS bit array used by larger nodes.
-// Output: for a node covering bits [o, o+N_v), u[o..o+N_v) = beta_v G_{N_v}
-// (the transform is its own inverse), so each decision node appends its
-// information bits, in index order, to a 64-bit scalar accumulator that is
-// stored 8 bytes at a time.
-//
-// Arithmetic: int8 LLRs follow Listing 4 (g saturates to [-127, 127]);
-// float LLRs use one IEEE add per g and the halving-tree repetition sum, so
-// both are bit-identical to a sequential decoder with the same definitions.
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
-#include "plan.h"
-
-#define LDS __attribute__((address_space(3)))
+// Schedule-interpreting Fast-SSC / SC decode kernel for gfx950: one
+// wavefront per frame runs the code's device schedule, read from memory at
+// run time, so one kernel serves every code.  The op implementations are in
+// decode_ops.h.
+#include "decode_ops.h"
 
 namespace polar {
-namespace {
-
-typedef short s2 __attribute__((ext_vector_type(2)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-
-// ---------------------------------------------------------------------------
-// Lane movement: lane i receives x from lane i + H.  Valid for every lane
-// whose bit H is clear (the lanes that need the partner element).
-// ---------------------------------------------------------------------------
-template <int H>
-__device__ __forceinline__ uint32_t from_up(uint32_t x) {
-  static_assert(H == 1 || H == 2 || H == 4 || H == 8 || H == 16 || H == 32, "lane distance");
-  if constexpr (H <= 8) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x100 + H, 0xf, 0xf, false);  // row_shl:H
-  } else if constexpr (H == 16) {
-    return __builtin_amdgcn_permlane16_swap(x, x, false, false)[1];
-  } else {
-    return __builtin_amdgcn_permlane32_swap(x, x, false, false)[1];
-  }
-}
-template <int H>
-__device__ __forceinline__ float from_up(float x) {
-  return __uint_as_float(from_up<H>(__float_as_uint(x)));
-}
-
-__device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__builtin_amdgcn_ballot_w64(p); }
-__device__ __forceinline__ bool lane_pred(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
-__device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ float rflf(float x) { return __uint_as_float(rfl(__float_as_uint(x))); }
-// Orders the wave's LDS traffic across lanes and keeps the compiler from
-// moving memory operations over op boundaries.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ uint64_t low_mask(int bits) { return bits >= 64 ? ~0ull : ((1ull << bits) - 1ull); }
-
-// u = x G on up to 64 bits: x[i] ^= x[i+h] for every i with bit h clear.
-__device__ __forceinline__ uint64_t transform64(uint64_t x, int size) {
-  if (size > 1) x ^= (x >> 1) & 0x5555555555555555ull;
-  if (size > 2) x ^= (x >> 2) & 0x3333333333333333ull;
-  if (size > 4) x ^= (x >> 4) & 0x0F0F0F0F0F0F0F0Full;
-  if (size > 8) x ^= (x >> 8) & 0x00FF00FF00FF00FFull;
-  if (size > 16) x ^= (x >> 16) & 0x0000FFFF0000FFFFull;
-  if (size > 32) x ^= (x >> 32) & 0x00000000FFFFFFFFull;
-  return x;
-}
-
-__device__ __forceinline__ uint32_t transform32(uint32_t x) {
-  x ^= (x >> 1) & 0x55555555u;
-  x ^= (x >> 2) & 0x33333333u;
-  x ^= (x >> 4) & 0x0F0F0F0Fu;
-  x ^= (x >> 8) & 0x00FF00FFu;
-  x ^= (x >> 16) & 0x0000FFFFu;
-  return x;
-}
-
-// ---------------------------------------------------------------------------
-// int8 LLRs as packed 16-bit integers scaled by 256 (the byte is the high
-// half of each 16-bit lane).  Sums are saturated by the packed add and then
-// clamped to +-127*256, which is exactly the 8-bit saturating g of
-// Listing 4 on the unscaled values.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ s2 as_s2(uint32_t x) { return __builtin_bit_cast(s2, x); }
-__device__ __forceinline__ uint32_t as_u(s2 x) { return __builtin_bit_cast(uint32_t, x); }
-__device__ __forceinline__ s2 unpack_lo(uint32_t w) { return as_s2(__builtin_amdgcn_perm(0u, w, 0x010c000cu)); }
-__device__ __forceinline__ s2 unpack_hi(uint32_t w) { return as_s2(__builtin_amdgcn_perm(0u, w, 0x030c020cu)); }
-__device__ __forceinline__ uint32_t pack4(s2 lo, s2 hi) {
-  return __builtin_amdgcn_perm(as_u(hi), as_u(lo), 0x07050301u);
-}
-__device__ __forceinline__ s2 sat127(s2 r) {
-  const s2 lo = {(short)-32512, (short)-32512}, hi = {(short)32512, (short)32512};
-  return __builtin_elementwise_min(__builtin_elementwise_max(r, lo), hi);
-}
-__device__ __forceinline__ s2 fx(s2 a, s2 b) {
-  return __builtin_elementwise_max(__builtin_elementwise_min(a, b), -__builtin_elementwise_max(a, b));
-}
-// s: +-1 per half (-1 where beta_l = 1)
-__device__ __forceinline__ s2 gx(s2 a, s2 b, s2 s) { return sat127(__builtin_elementwise_add_sat(b, a * s)); }
-__device__ __forceinline__ s2 g0x(s2 a, s2 b) { return sat127(__builtin_elementwise_add_sat(b, a)); }
-// channel value -128 is read as -127
-__device__ __forceinline__ s2 chanx(s2 a) {
-  const s2 lo = {(short)-32512, (short)-32512};
-  return __builtin_elementwise_max(a, lo);
-}
-
-// ---------------------------------------------------------------------------
-// Arithmetic policies
-// ---------------------------------------------------------------------------
-struct PI8 {
-  typedef int8_t Chan;
-  static constexpr int ELEM = 1;
-  static __device__ __forceinline__ float clamp32(float x) { return __builtin_amdgcn_fmed3f(x, -127.0f, 127.0f); }
-  static __device__ __forceinline__ float chan(int v) { return (float)(v < -127 ? -127 : v); }
-  static __device__ __forceinline__ int8_t to_chan(float v) { return (int8_t)(int)v; }
-};
-
-struct PF32 {
-  typedef float Chan;
-  static constexpr int ELEM = 4;
-  static __device__ __forceinline__ float clamp32(float x) { return x; }
-  static __device__ __forceinline__ float to_chan(float v) { return v; }
-};
-
-__device__ __forceinline__ float fmin_sum(float x, float y) { return fmaxf(fminf(x, y), fminf(-x, -y)); }
-
-// ---------------------------------------------------------------------------
-// Per-wave decoder
-// ---------------------------------------------------------------------------
-template <class P>
-struct Dec {
-  typedef typename P::Chan Chan;
-
-  int lane;
-  int log2n;
-  LDS unsigned char* alpha;   // stage s (7 <= s < log2n) at alpha + (2^s - 128) * ELEM
-  LDS uint32_t* beta;         // N bits, natural order
-  LDS uint32_t* lut;          // int8 g signs: 16 entries of two +-1 pairs
-  __amdgpu_buffer_rsrc_t chr; // channel row
-  Chan* tr;                   // trace row (global) or null
-  uint8_t* row;               // output row (global)
-  int row_bytes;
-
-  float a[7];                 // stages 0..6
-  uint64_t win;               // beta of the current 64-aligned block
-  uint64_t acc;               // output accumulator
-  int fill;                   // bits held in acc
-  int words_out;              // 64-bit output words stored so far
-  uint64_t pend_v;            // bits the last op wants appended ...
-  int pend_n;                 // ... and how many (0: none)
-  int pend_bits;              // > 0: emit u = x G of this many beta bits at pend_p
-  int pend_p;                 // dword offset of those bits in the beta array
-  int pend_flags;             // 1: skip u_0 (SPC); 2: undo the transform afterwards
-
-  __device__ __forceinline__ LDS unsigned char* stage(int s) const { return alpha + ((1 << s) - 128) * P::ELEM; }
-
-  // ------------------------------------------------------------- output
-  __device__ __forceinline__ void emit(uint64_t w) {
-    const int idx = 8 * words_out + lane;
-    if (lane < 8 && idx < row_bytes) row[idx] = (uint8_t)(w >> (8 * lane));
-    ++words_out;
-  }
-  // append the low n bits of v (1 <= n <= 64; higher bits must be 0)
-  __device__ __forceinline__ void append(uint64_t v, int n) {
-    acc |= v << fill;
-    const int nf = fill + n;
-    if (nf >= 64) {
-      emit(acc);
-      acc = fill ? (v >> (64 - fill)) : 0ull;
-      fill = nf - 64;
-    } else {
-      fill = nf;
-    }
-  }
-
-  // u = x G over nbits (>= 128, power of two) of the beta array starting at
-  // dword p, in place.  Lane L holds dwords L, L+64, ...
-  __device__ __forceinline__ void transform_bits(int p, int nbits) {
-    const int words = nbits >> 5;
-    for (int w = lane; w < words; w += 64) beta[p + w] = transform32(beta[p + w]);
-    wave_sync();
-    for (int d = 1; d < words; d <<= 1) {
-      for (int w = lane; w < words; w += 64)
-        if ((w & d) == 0) beta[p + w] ^= beta[p + w + d];
-      wave_sync();
-    }
-  }
-
-  // Output work recorded by the last op (one copy of this code in the loop).
-  __device__ __forceinline__ void settle() {
-    if (pend_n) {
-      append(pend_v, pend_n);
-      pend_n = 0;
-    }
-    if (pend_bits) {
-      const int p = pend_p;
-      transform_bits(p, pend_bits);
-      const LDS u32x2* q = (const LDS u32x2*)(beta + p);
-      for (int t = 0; t < pend_bits / 64; ++t) {
-        const u32x2 v2 = q[t];  // the same address in every lane: a broadcast
-        const uint64_t v = ((uint64_t)rfl(v2[1]) << 32) | rfl(v2[0]);
-        if (t == 0 && (pend_flags & 1))
-          append(v >> 1, 63);
-        else
-          append(v, 64);
-      }
-      wave_sync();
-      if (pend_flags & 2) transform_bits(p, pend_bits);
-      pend_bits = 0;
-    }
-  }
-
-  // ------------------------------------------------- nodes of size <= 64
-  template <int S>
-  __device__ __forceinline__ void small_fg(uint32_t code, int o) {
-    constexpr int H = 1 << (S - 1);
-    const float x = a[S];
-    const float y = from_up<H>(x);
-    if (code == DOP_F) {
-      a[S - 1] = fmin_sum(x, y);
-    } else if (code == DOP_G) {
-      const bool neg = lane_pred(win >> (o & 63));
-      a[S - 1] = P::clamp32(y + (neg ? -x : x));
-    } else {
-      a[S - 1] = P::clamp32(y + x);
-    }
-  }
-
-  __device__ __forceinline__ void set_win(int off, uint64_t m, uint64_t bits) {
-    win = (win & ~(m << off)) | (bits << off);
-  }
-
-  template <int S>
-  __device__ __forceinline__ void small_leaf(uint32_t code, int o) {
-    constexpr int NV = 1 << S;
-    const int off = o & 63;
-    const uint64_t m = low_mask(NV);
-    const float x = a[S];
-    if (tr && lane < NV) tr[o + lane] = P::to_chan(x);
-    uint64_t hd = ballot(x < 0.0f) & m;
-    if (code == DOP_R1) {
-      set_win(off, m, hd);
-      pend_v = transform64(hd, NV);
-      pend_n = NV;
-    } else if (code == DOP_REP) {
-      float s = x;
-      if constexpr (NV >= 64) s += from_up<32>(s);
-      if constexpr (NV >= 32) s += from_up<16>(s);
-      if constexpr (NV >= 16) s += from_up<8>(s);
-      if constexpr (NV >= 8) s += from_up<4>(s);
-      if constexpr (NV >= 4) s += from_up<2>(s);
-      if constexpr (NV >= 2) s += from_up<1>(s);
-      const bool bit = rflf(s) < 0.0f;
-      set_win(off, m, bit ? m : 0ull);
-      pend_v = bit ? 1ull : 0ull;
-      pend_n = 1;
-    } else {  // DOP_SPC
-      if (__popcll(hd) & 1) {
-        float v = lane < NV ? fabsf(x) : 3.0e38f;
-        if constexpr (NV >= 64) v = fminf(v, from_up<32>(v));
-        if constexpr (NV >= 32) v = fminf(v, from_up<16>(v));
-        if constexpr (NV >= 16) v = fminf(v, from_up<8>(v));
-        if constexpr (NV >= 8) v = fminf(v, from_up<4>(v));
-        if constexpr (NV >= 4) v = fminf(v, from_up<2>(v));
-        if constexpr (NV >= 2) v = fminf(v, from_up<1>(v));
-        const float mn = rflf(v);
-        const uint64_t cand = ballot(lane < NV && fabsf(x) == mn);
-        hd ^= 1ull << (__ffsll((unsigned long long)cand) - 1);
-      }
-      set_win(off, m, hd);
-      pend_v = transform64(hd, NV) >> 1;
-      pend_n = NV - 1;
-    }
-  }
-
-  __device__ __forceinline__ void small_combine(uint32_t code, int S, int o) {
-    const int h = 1 << (S - 1);
-    const int off = o & 63;
-    const uint64_t m = low_mask(h);
-    const uint64_t r = (win >> (off + h)) & m;
-    if (code == DOP_C)
-      win ^= r << off;
-    else if (code == DOP_C0R)
-      set_win(off, m, r);
-    else
-      win &= ~(m << (off + h));
-  }
-
-  // ------------------------------------------ big nodes: beta in LDS bits
-  __device__ __forceinline__ void big_combine(uint32_t code, int S, int o) {
-    const int h = 1 << (S - 1);
-    const int words = h >> 5;
-    LDS uint32_t* l = beta + (o >> 5);
-    LDS uint32_t* r = beta + ((o + h) >> 5);
-    for (int j = lane; j < words; j += 64) {
-      if (code == DOP_C)
-        l[j] ^= r[j];
-      else if (code == DOP_C0R)
-        l[j] = r[j];
-      else
-        r[j] = 0u;
-    }
-  }
-
-  // window of a finished size-64 node -> LDS bits
-  __device__ __forceinline__ void flush(int o) {
-    if (lane < 2) beta[(o >> 5) + lane] = (uint32_t)(win >> (32 * lane));
-  }
-
-  // ---------------------------------------- stage 7 -> stage 6 (registers)
-  __device__ __forceinline__ float load7(int i) {
-    // element i of the input of an op at stage 7 (LDS stage 7 or channel)
-    if (log2n == 7) {
-      if constexpr (P::ELEM == 1)
-        return P::chan((int)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(chr, i, 0, 0));
-      else
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(chr, 4 * i, 0, 0));
-    }
-    if constexpr (P::ELEM == 1)
-      return (float)*(const LDS int8_t*)(stage(7) + i);
-    else
-      return *(const LDS float*)(stage(7) + 4 * i);
-  }
-
-  __device__ __forceinline__ void fg7(uint32_t code) {
-    const float x = load7(lane), y = load7(lane + 64);
-    if (code == DOP_F)
-      a[6] = fmin_sum(x, y);
-    else if (code == DOP_G)
-      a[6] = P::clamp32(y + (lane_pred(win) ? -x : x));  // beta of the left size-64 child
-    else
-      a[6] = P::clamp32(y + x);
-  }
-
-  // ------------------------------------------------- big F / G / G_0R
-  // int8: lane chunks of CB bytes (CB = 16, or 4 for nodes below 4096).
-  template <int CB, bool CH, uint32_t CODE>
-  __device__ __forceinline__ void i8_fg(int S, int o) {
-    const int h = 1 << (S - 1);
-    const LDS unsigned char* in = stage(S);
-    LDS unsigned char* out = stage(S - 1);
-    constexpr int NW = CB / 4;
-    for (int base = 0; base < h; base += 64 * CB) {
-      const int i0 = base + lane * CB;
-      if (i0 < h) {
-        uint32_t A[NW], B[NW], R[NW];
-        if constexpr (CH) {
-          if constexpr (CB == 16) {
-            const u32x4 va = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(chr, i0, 0, 0));
-            const u32x4 vb = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(chr, i0 + h, 0, 0));
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              A[k] = va[k];
-              B[k] = vb[k];
-            }
-          } else {
-            A[0] = __builtin_amdgcn_raw_buffer_load_b32(chr, i0, 0, 0);
-            B[0] = __builtin_amdgcn_raw_buffer_load_b32(chr, i0 + h, 0, 0);
-          }
-        } else {
-          if constexpr (CB == 16) {
-            const u32x4 va = *(const LDS u32x4*)(in + i0);
-            const u32x4 vb = *(const LDS u32x4*)(in + i0 + h);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              A[k] = va[k];
-              B[k] = vb[k];
-            }
-          } else {
-            A[0] = *(const LDS uint32_t*)(in + i0);
-            B[0] = *(const LDS uint32_t*)(in + i0 + h);
-          }
-        }
-        uint32_t bb = 0;
-        if constexpr (CODE == DOP_G) bb = beta[(o + i0) >> 5] >> ((o + i0) & 31);
-#pragma unroll
-        for (int k = 0; k < NW; ++k) {
-          s2 al = unpack_lo(A[k]), ah = unpack_hi(A[k]);
-          s2 bl = unpack_lo(B[k]), bh = unpack_hi(B[k]);
-          if constexpr (CH) {
-            al = chanx(al);
-            ah = chanx(ah);
-            bl = chanx(bl);
-            bh = chanx(bh);
-          }
-          s2 rl, rh;
-          if constexpr (CODE == DOP_F) {
-            rl = fx(al, bl);
-            rh = fx(ah, bh);
-          } else if constexpr (CODE == DOP_G) {
-            const u32x2 sg = *(const LDS u32x2*)(lut + 2 * ((bb >> (4 * k)) & 15u));
-            rl = gx(al, bl, as_s2(sg[0]));
-            rh = gx(ah, bh, as_s2(sg[1]));
-          } else {
-            rl = g0x(al, bl);
-            rh = g0x(ah, bh);
-          }
-          R[k] = pack4(rl, rh);
-        }
-        if constexpr (CB == 16)
-          *(LDS u32x4*)(out + i0) = (u32x4){R[0], R[1], R[2], R[3]};
-        else
-          *(LDS uint32_t*)(out + i0) = R[0];
-      }
-    }
-  }
-
-  // float: lane chunks of 4 values (16 bytes).
-  template <bool CH, uint32_t CODE>
-  __device__ __forceinline__ void f32_fg(int S, int o) {
-    const int h = 1 << (S - 1);
-    const LDS float* in = (const LDS float*)stage(S);
-    LDS float* out = (LDS float*)stage(S - 1);
-    for (int base = 0; base < h; base += 256) {
-      const int i0 = base + lane * 4;
-      if (i0 < h) {
-        float A[4], B[4], R[4];
-        u32x4 va, vb;
-        if constexpr (CH) {
-          va = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(chr, 4 * i0, 0, 0));
-          vb = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(chr, 4 * (i0 + h), 0, 0));
-        } else {
-          va = *(const LDS u32x4*)(in + i0);
-          vb = *(const LDS u32x4*)(in + i0 + h);
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          A[k] = __uint_as_float(va[k]);
-          B[k] = __uint_as_float(vb[k]);
-        }
-        uint32_t bb = 0;
-        if constexpr (CODE == DOP_G) bb = beta[(o + i0) >> 5] >> ((o + i0) & 31);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if constexpr (CODE == DOP_F)
-            R[k] = fmin_sum(A[k], B[k]);
-          else if constexpr (CODE == DOP_G)  // b + (-a) is exactly b - a
-            R[k] = __fadd_rn(B[k], __uint_as_float(__float_as_uint(A[k]) ^ ((bb << (31 - k)) & 0x80000000u)));
-          else
-            R[k] = __fadd_rn(B[k], A[k]);
-        }
-        *(LDS u32x4*)(out + i0) =
-            (u32x4){__float_as_uint(R[0]), __float_as_uint(R[1]), __float_as_uint(R[2]), __float_as_uint(R[3])};
-      }
-    }
-  }
-
-  template <uint32_t CODE>
-  __device__ __forceinline__ void big_fg_code(int S, int o) {
-    const bool ch = S == log2n;
-    if constexpr (P::ELEM == 1) {
-      if (S >= 12) {
-        if (ch)
-          i8_fg<16, true, CODE>(S, o);
-        else
-          i8_fg<16, false, CODE>(S, o);
-      } else {
-        if (ch)
-          i8_fg<4, true, CODE>(S, o);
-        else
-          i8_fg<4, false, CODE>(S, o);
-      }
-    } else {
-      if (ch)
-        f32_fg<true, CODE>(S, o);
-      else
-        f32_fg<false, CODE>(S, o);
-    }
-  }
-
-  __device__ __forceinline__ void big_fg(uint32_t code, int S, int o) {
-    if (S == 7) {
-      fg7(code);
-      return;
-    }
-    if (code == DOP_F)
-      big_fg_code<DOP_F>(S, o);
-    else if (code == DOP_G)
-      big_fg_code<DOP_G>(S, o);
-    else
-      big_fg_code<DOP_G0R>(S, o);
-  }
-
-  // ------------------------------------------------------- big leaves
-  // Elements i0 .. i0+3 of the input of a leaf at stage S (LDS or channel).
-  __device__ __forceinline__ void leaf_quad(int S, int i0, float* v) {
-    if constexpr (P::ELEM == 1) {
-      uint32_t w;
-      if (S == log2n)
-        w = __builtin_amdgcn_raw_buffer_load_b32(chr, i0, 0, 0);
-      else
-        w = *(const LDS uint32_t*)(stage(S) + i0);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int x = (int)(int8_t)(w >> (8 * k));
-        v[k] = (float)(x < -127 ? -127 : x);
-      }
-    } else {
-      u32x4 q;
-      if (S == log2n)
-        q = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(chr, 4 * i0, 0, 0));
-      else
-        q = *(const LDS u32x4*)(stage(S) + 4 * i0);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) v[k] = __uint_as_float(q[k]);
-    }
-  }
-
-  __device__ __forceinline__ void big_leaf(uint32_t code, int S, int o) {
-    const int nv = 1 << S;
-    LDS uint32_t* bw = beta + (o >> 5);
-    if (code == DOP_REP) {
-      float s;
-      if constexpr (P::ELEM == 1) {
-        // integers: every partial sum is exact, so the order is free
-        int acc_i = 0;
-        for (int i0 = 4 * lane; i0 < nv; i0 += 256) {
-          float v[4];
-          leaf_quad(S, i0, v);
-          if (tr)
-            for (int k = 0; k < 4; ++k) tr[o + i0 + k] = P::to_chan(v[k]);
-          acc_i += (int)v[0] + (int)v[1] + (int)v[2] + (int)v[3];
-        }
-        s = (float)acc_i;
-        s += __shfl_xor(s, 32, 64);
-        s += __shfl_xor(s, 16, 64);
-        s += __shfl_xor(s, 8, 64);
-        s += __shfl_xor(s, 4, 64);
-        s += __shfl_xor(s, 2, 64);
-        s += __shfl_xor(s, 1, 64);
-      } else {
-        s = rep_halving_f32(S, o);
-      }
-      const bool bit = rflf(s) < 0.0f;
-      for (int j = lane; j < (nv >> 5); j += 64) bw[j] = bit ? ~0u : 0u;
-      pend_v = bit ? 1ull : 0ull;
-      pend_n = 1;
-      return;
-    }
-    // Rate-1 / SPC: hard decisions, 32 elements (one beta word) per lane
-    int parity = 0;
-    float best = 3.0e38f;
-    int best_i = 0x7fffffff;
-    for (int j = lane; j < (nv >> 5); j += 64) {
-      uint32_t d = 0;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        float v[4];
-        leaf_quad(S, 32 * j + 4 * q, v);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int i = 32 * j + 4 * q + k;
-          if (tr) tr[o + i] = P::to_chan(v[k]);
-          d |= (v[k] < 0.0f ? 1u : 0u) << (4 * q + k);
-          const float mg = fabsf(v[k]);
-          if (mg < best) {
-            best = mg;
-            best_i = i;
-          }
-        }
-      }
-      bw[j] = d;
-      parity ^= __popc(d) & 1;
-    }
-    if (code == DOP_SPC && (__popcll(ballot(parity != 0)) & 1)) {
-      float v = best;
-      v = fminf(v, __shfl_xor(v, 32, 64));
-      v = fminf(v, __shfl_xor(v, 16, 64));
-      v = fminf(v, __shfl_xor(v, 8, 64));
-      v = fminf(v, __shfl_xor(v, 4, 64));
-      v = fminf(v, __shfl_xor(v, 2, 64));
-      v = fminf(v, __shfl_xor(v, 1, 64));
-      int idx = (best == v) ? best_i : 0x7fffffff;
-      idx = min(idx, __shfl_xor(idx, 32, 64));
-      idx = min(idx, __shfl_xor(idx, 16, 64));
-      idx = min(idx, __shfl_xor(idx, 8, 64));
-      idx = min(idx, __shfl_xor(idx, 4, 64));
-      idx = min(idx, __shfl_xor(idx, 2, 64));
-      idx = min(idx, __shfl_xor(idx, 1, 64));
-      idx = (int)rfl((uint32_t)idx);
-      wave_sync();
-      if (lane == 0) bw[idx >> 5] ^= 1u << (idx & 31);
-    }
-    wave_sync();
-    // information bits: u = beta G over the node, computed in place and
-    // undone afterwards unless this is the root
-    pend_bits = nv;
-    pend_p = o >> 5;
-    pend_flags = (code == DOP_SPC ? 1 : 0) | (S < log2n ? 2 : 0);
-  }
-
-  // Halving-tree repetition sum of a float leaf: the levels above 64 run in
-  // place in the LDS buffer of the stage below (dead at a leaf), the last
-  // 64 across lanes.
-  __device__ __forceinline__ float rep_halving_f32(int S, int o) {
-    const int nv = 1 << S;
-    const bool ch = S == log2n;
-    if (tr)
-      for (int i = lane; i < nv; i += 64) {
-        float v;
-        if (ch)
-          v = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(chr, 4 * i, 0, 0));
-        else
-          v = ((const LDS float*)stage(S))[i];
-        tr[o + i] = v;
-      }
-    float v;
-    if (nv == 128) {
-      // one level: lane i adds elements i and i + 64
-      if (ch) {
-        v = __fadd_rn(__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(chr, 4 * lane, 0, 0)),
-                      __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(chr, 4 * (lane + 64), 0, 0)));
-      } else {
-        v = __fadd_rn(((const LDS float*)stage(S))[lane], ((const LDS float*)stage(S))[lane + 64]);
-      }
-    } else {
-      // nv >= 256: stage S-1 >= 7 exists and is dead at a leaf
-      LDS float* buf = (LDS float*)stage(S - 1);
-      // level m = nv: s_i = x_i + x_{i + nv/2}
-      for (int i = lane; i < nv / 2; i += 64) {
-        float x, y;
-        if (ch) {
-          x = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(chr, 4 * i, 0, 0));
-          y = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(chr, 4 * (i + nv / 2), 0, 0));
-        } else {
-          x = ((const LDS float*)stage(S))[i];
-          y = ((const LDS float*)stage(S))[i + nv / 2];
-        }
-        buf[i] = __fadd_rn(x, y);
-      }
-      wave_sync();
-      for (int m = nv / 2; m > 64; m >>= 1) {
-        for (int i = lane; i < m / 2; i += 64) buf[i] = __fadd_rn(buf[i], buf[i + m / 2]);
-        wave_sync();
-      }
-      v = buf[lane];
-    }
-    v = __fadd_rn(v, from_up<32>(v));
-    v = __fadd_rn(v, from_up<16>(v));
-    v = __fadd_rn(v, from_up<8>(v));
-    v = __fadd_rn(v, from_up<4>(v));
-    v = __fadd_rn(v, from_up<2>(v));
-    v = __fadd_rn(v, from_up<1>(v));
-    return v;
-  }
-
-  // ----------------------------------------------------------- dispatch
-  __device__ __forceinline__ void small_op(uint32_t code, int S, int o) {
-    if (code <= DOP_G0R) {
-      switch (S) {
-        case 1: small_fg<1>(code, o); break;
-        case 2: small_fg<2>(code, o); break;
-        case 3: small_fg<3>(code, o); break;
-        case 4: small_fg<4>(code, o); break;
-        case 5: small_fg<5>(code, o); break;
-        default: small_fg<6>(code, o); break;
-      }
-    } else if (code <= DOP_CR0) {
-      small_combine(code, S, o);
-    } else if (code == DOP_FLUSH) {
-      flush(o);
-    } else {
-      switch (S) {
-        case 0: small_leaf<0>(code, o); break;
-        case 1: small_leaf<1>(code, o); break;
-        case 2: small_leaf<2>(code, o); break;
-        case 3: small_leaf<3>(code, o); break;
-        case 4: small_leaf<4>(code, o); break;
-        case 5: small_leaf<5>(code, o); break;
-        default: small_leaf<6>(code, o); break;
-      }
-    }
-  }
-
-  __device__ __forceinline__ void op(uint32_t w0) {
-    const uint32_t code = w0 & 0xffu;
-    const int S = (int)((w0 >> 8) & 0xffu);
-    const int o = (int)(w0 >> 16);
-    if (S <= 6)
-      small_op(code, S, o);
-    else if (code <= DOP_G0R)
-      big_fg(code, S, o);
-    else if (code <= DOP_CR0)
-      big_combine(code, S, o);
-    else
-      big_leaf(code, S, o);
-  }
-};
-
-}  // namespace
-
-__host__ __device__ constexpr int align16(int x) { return (x + 15) & ~15; }
-
-// LDS bytes one wave needs: the g sign table, stages 7..log2n-1, N-bit beta.
-int wave_lds_bytes(int log2n, int, int llr_type) {
-  const int elem = llr_type == 1 ? 4 : 1;
-  const int n = 1 << log2n;
-  const int alpha = log2n > 7 ? (n - 128) * elem : 0;
-  const int beta = log2n > 6 ? n / 8 : 0;
-  return 128 + align16(alpha) + align16(beta);
-}
 
 template <class P>
 __global__ void __launch_bounds__(256) decode_kernel(const uint32_t* __restrict__ ops, int nops, int log2n,
@@ -731,54 +18,8 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint32_t* __restrict_
   const int frame = blockIdx.x * (blockDim.x >> 6) + wid;
   if (frame >= nframes) return;  // no block-level barriers follow
 
-  typedef Dec<P> D;
-  const int n = 1 << log2n;
-  LDS unsigned char* base = (LDS unsigned char*)smem + wid * wave_bytes;
-  D d;
-  d.lane = lane;
-  d.log2n = log2n;
-  d.lut = (LDS uint32_t*)base;
-  d.alpha = base + 128;
-  d.beta = (LDS uint32_t*)(base + 128 + align16(log2n > 7 ? (n - 128) * P::ELEM : 0));
-  d.chr = __builtin_amdgcn_make_buffer_rsrc((void*)(llr + (size_t)frame * n), 0, n * (int)sizeof(typename P::Chan),
-                                            0x00020000);
-  d.tr = trace ? trace + (size_t)frame * n : nullptr;
-  d.row_bytes = (kbits + 7) / 8;
-  d.row = bits + (size_t)frame * d.row_bytes;
-  d.win = 0;
-  d.acc = 0;
-  d.fill = 0;
-  d.words_out = 0;
-  d.pend_v = 0;
-  d.pend_n = 0;
-  d.pend_bits = 0;
-  d.pend_p = 0;
-  d.pend_flags = 0;
-#pragma unroll
-  for (int s = 0; s < 7; ++s) d.a[s] = 0.0f;
-  // g sign table: entry e (4 beta bits) -> two +-1 pairs
-  if (lane < 32) {
-    const int e = lane >> 1, half = lane & 1;
-    const uint32_t b0 = (e >> (2 * half)) & 1u, b1 = (e >> (2 * half + 1)) & 1u;
-    d.lut[lane] = (b0 ? 0x0000FFFFu : 0x00000001u) | (b1 ? 0xFFFF0000u : 0x00010000u);
-  }
-  if (log2n <= 6) {
-    float x;
-    if constexpr (P::ELEM == 1)
-      x = P::chan((int)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(d.chr, lane, 0, 0));
-    else
-      x = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(d.chr, 4 * lane, 0, 0));
-    x = lane < n ? x : 0.0f;
-    switch (log2n) {
-      case 1: d.a[1] = x; break;
-      case 2: d.a[2] = x; break;
-      case 3: d.a[3] = x; break;
-      case 4: d.a[4] = x; break;
-      case 5: d.a[5] = x; break;
-      default: d.a[6] = x; break;
-    }
-  }
-  wave_sync();
+  Dec<P> d;
+  d.init((LDS unsigned char*)smem + wid * wave_bytes, lane, log2n, kbits, llr, frame, bits, trace);
 
   // The schedule is read 64 ops at a time, one op per lane, with the next
   // block in flight; each op is taken out of the block with readlane.  The
@@ -791,19 +32,14 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint32_t* __restrict_
     asm volatile("v_mov_b32 %0, %1" : "=v"(blk) : "v"(nxt));
     nxt = __builtin_amdgcn_raw_buffer_load_b32(opr, 4 * (pb + 64 + lane), 0, 0);
     const int cnt = (int)rfl((uint32_t)min(64, nops - pb));
-    for (int j = 0; j < cnt; ++j) {
-      const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)blk, j);
-      d.op(w0);
-      d.settle();
-      wave_sync();
-    }
+    for (int j = 0; j < cnt; ++j) d.step((uint32_t)__builtin_amdgcn_readlane((int)blk, j));
   }
-  if (d.fill > 0) d.emit(d.acc);
+  d.finish();
 }
 
 int launch_decode(const uint32_t* ops, int nops, int log2n, int kbits, int llr_type, const void* llr, int nframes,
                   uint8_t* bits, void* trace, int waves_per_block, void* stream) {
-  const int wb = wave_lds_bytes(log2n, kbits, llr_type);
+  const int wb = wave_lds_bytes(log2n, llr_type == 1 ? 4 : 1);
   const dim3 grid((nframes + waves_per_block - 1) / waves_per_block), block(64 * waves_per_block);
   const size_t lds = (size_t)wb * waves_per_block;
   hipStream_t s = (hipStream_t)stream;
@@ -816,7 +52,7 @@ int launch_decode(const uint32_t* ops, int nops, int log2n, int kbits, int llr_t
   return (int)hipGetLastError();
 }
 
-int set_lds_limit(int llr_type, int, int bytes) {
+int set_lds_limit(int llr_type, int bytes) {
   hipError_t e;
   if (llr_type == 1)
     e = hipFuncSetAttribute((const void*)decode_kernel<PF32>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);

@@ -1,0 +1,44 @@
+// Device op codes of the decoder schedule, shared by the host schedule
+// builder, the schedule-interpreting kernel and the generated per-code
+// kernels.  Plain C++ with no includes so that the run-time compiler can
+// take it as is.
+#pragma once
+
+namespace polar {
+
+// One op is one 32-bit word:  code | stage << 8 | node_offset << 16.
+// "stage" is log2 of the node size Nv; F/G/G0R read stage k and write
+// stage k-1; leaves and combines act on a node of stage k.  Decision nodes
+// append their information bits to the output in schedule order, which is
+// increasing index order.
+enum DeviceOp : unsigned {
+  DOP_F = 0,      // eq. (1) into the left child
+  DOP_G = 1,      // eq. (2) into the right child
+  DOP_G0R = 2,    // eq. (2) with a Rate-0 left child (beta_l = 0)
+  DOP_C = 3,      // eq. (3) combine
+  DOP_C0R = 4,    // combine with a Rate-0 left child (copy)
+  DOP_CR0 = 5,    // combine with a Rate-0 right child (clear the right half)
+  DOP_R1 = 6,     // Rate-1 leaf, eq. (4)
+  DOP_REP = 7,    // repetition leaf (Sec. II-E)
+  DOP_SPC = 8,    // single-parity-check leaf (Sec. II-E)
+  DOP_FLUSH = 9,  // write the 64-bit beta window of a finished size-64 node to LDS
+  DOP_END = 10,   // padding after the last op
+};
+
+constexpr int kRegStages = 6;  // stages 0..6 (sizes 1..64) are register resident
+constexpr int kMaxLog2N = 15;  // N <= 32768
+constexpr int kMaxN = 1 << kMaxLog2N;
+
+constexpr unsigned pack_op(unsigned code, int stage, int offset) {
+  return code | ((unsigned)stage << 8) | ((unsigned)offset << 16);
+}
+
+// LDS bytes one wavefront needs: a 128-byte g sign table, the alpha stages
+// 7..log2n-1 (elem bytes per LLR) and the N-bit beta array, each 16-byte
+// aligned.
+constexpr int wave_lds_bytes(int log2n, int elem) {
+  return 128 + (((log2n > 7 ? ((1 << log2n) - 128) * elem : 0) + 15) & ~15) +
+         (((log2n > 6 ? (1 << log2n) / 8 : 0) + 15) & ~15);
+}
+
+}  // namespace polar

@@ -5,6 +5,8 @@
 
 #include <vector>
 
+#include "opcodes.h"
+
 namespace polar {
 
 // Decoder-tree node functions (the vocabulary of Listing 1) as they appear
@@ -20,34 +22,6 @@ enum LogicalOp : int32_t {
   LOP_SPC = 7,    // single-parity-check leaf (Sec. II-E)
   LOP_CR0 = 8,    // combine with a Rate-0 right child (arbitrary masks only)
 };
-
-// Device op codes.  One op is one 32-bit word:
-//   code | stage << 8 | node_offset << 16      (node_offset < 2^16)
-// "stage" is log2 of the node size Nv; F/G/G0R read stage k and write
-// stage k-1; leaves and combines act on a node of stage k.  Decision nodes
-// append their information bits to the output in schedule order, which is
-// increasing index order.
-enum DeviceOp : uint32_t {
-  DOP_F = 0,
-  DOP_G = 1,
-  DOP_G0R = 2,
-  DOP_C = 3,
-  DOP_C0R = 4,
-  DOP_CR0 = 5,
-  DOP_R1 = 6,
-  DOP_REP = 7,
-  DOP_SPC = 8,
-  DOP_FLUSH = 9,  // write the 64-bit beta window of a finished size-64 node to LDS
-  DOP_END = 10,   // padding after the last op
-};
-
-constexpr int kRegStages = 6;       // stages 0..6 (sizes 1..64) are register resident
-constexpr int kMaxLog2N = 15;       // N <= 32768
-constexpr int kMaxN = 1 << kMaxLog2N;
-
-inline uint32_t pack_op(uint32_t code, int stage, int offset) {
-  return code | ((uint32_t)stage << 8) | ((uint32_t)offset << 16);
-}
 
 struct Plan {
   int n = 0;        // code length N

@@ -1,0 +1,219 @@
+// Generated per-code decode kernels: the unrolled decoder of Sec. III-B, a
+// decoder specialised to one frozen set with no run-time schedule, written
+// as the list of node-function calls of Listing 1 (Sec. III-B.1) with every
+// size and offset a compile-time constant (Sec. III-B.4).
+//
+// The device schedule of a code is written out as a straight sequence of
+// op calls, each with its op word as a literal, into a small HIP source
+// that includes the same op library as the schedule-interpreting kernel
+// (decode_ops.h).  With every op argument a constant the compiler removes
+// all dispatch, folds the output bookkeeping and keeps every node size and
+// offset static, so the kernel does the same arithmetic in the same order as
+// the interpreter, without its per-op cost.
+//
+// Compiled code objects are cached on disk under a key that hashes the
+// source, the compile options and the compiler version, so a code is
+// compiled once per machine image; polar_build_kernel() fills the cache
+// ahead of time without a device.
+#include <dlfcn.h>
+#include <hip/hip_runtime_api.h>
+#include <hip/hiprtc.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <string>
+#include <vector>
+
+#include "embedded_headers.inc"  // kOpcodesH, kDecodeOpsH: the op library as text
+#include "unrolled.h"
+
+namespace polar {
+
+namespace {
+
+const char* const kOptions[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+                                "-fno-honor-nans", "-fno-honor-infinities", "-Xclang", "-target-feature",
+                                "-Xclang", "-packed-fp32-ops"};
+constexpr int kNumOptions = sizeof(kOptions) / sizeof(kOptions[0]);
+
+uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
+  const unsigned char* p = (const unsigned char*)data;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+std::string library_dir() {
+  Dl_info info;
+  if (dladdr((void*)&library_dir, &info) && info.dli_fname) {
+    std::string p(info.dli_fname);
+    const size_t s = p.rfind('/');
+    if (s != std::string::npos) return p.substr(0, s);
+  }
+  return ".";
+}
+
+std::string cache_dir() {
+  const char* env = getenv("POLAR_KERNEL_CACHE");
+  if (env && *env) return env;
+  return library_dir() + "/kernels";
+}
+
+bool read_file(const std::string& path, std::vector<char>& out) {
+  FILE* f = fopen(path.c_str(), "rb");
+  if (!f) return false;
+  fseek(f, 0, SEEK_END);
+  const long sz = ftell(f);
+  fseek(f, 0, SEEK_SET);
+  out.resize(sz > 0 ? (size_t)sz : 0);
+  const bool ok = sz > 0 && fread(out.data(), 1, out.size(), f) == out.size();
+  fclose(f);
+  return ok;
+}
+
+bool write_file_atomic(const std::string& path, const std::vector<char>& data) {
+  const std::string tmp = path + ".tmp." + std::to_string((long)getpid());
+  FILE* f = fopen(tmp.c_str(), "wb");
+  if (!f) return false;
+  const bool ok = fwrite(data.data(), 1, data.size(), f) == data.size();
+  if (fclose(f) != 0 || !ok) {
+    unlink(tmp.c_str());
+    return false;
+  }
+  if (rename(tmp.c_str(), path.c_str()) != 0) {
+    unlink(tmp.c_str());
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+std::string unrolled_source(const Plan& p, int llr_type) {
+  const char* pol = llr_type == 1 ? "PF32" : "PI8";
+  const char* chan = llr_type == 1 ? "float" : "int8_t";
+  std::string s;
+  s.reserve(64 * (size_t)p.nops + 4096);
+  s += "// generated: unrolled decoder for one polar code\n";
+  s += "// N=" + std::to_string(p.n) + " K=" + std::to_string(p.k) + " algo=" + std::to_string(p.algo) +
+       " llr=" + std::to_string(llr_type) + " ops=" + std::to_string(p.nops) + "\n";
+  s += "#include \"decode_ops.h\"\n\nnamespace {\n\n";
+  s += "template <class D>\n__device__ __forceinline__ void run(D& d) {\n";
+  char line[80];
+  for (int i = 0; i < p.nops; ++i) {
+    snprintf(line, sizeof line, "  d.template step_c<0x%08xu, %d>();\n", p.dops[i], p.log2n);
+    s += line;
+  }
+  s += "}\n\n";
+  s += "__device__ __forceinline__ void entry(const " + std::string(chan) + "* llr, int nframes, uint8_t* bits, " +
+       chan + "* trace, int wave_bytes, unsigned char* smem) {\n";
+  s += "  const int lane = threadIdx.x & 63;\n";
+  s += "  const int wid = (int)polar::rfl(threadIdx.x >> 6);\n";
+  s += "  const int frame = blockIdx.x * (blockDim.x >> 6) + wid;\n";
+  s += "  if (frame >= nframes) return;\n";
+  s += "  polar::Dec<polar::" + std::string(pol) + "> d;\n";
+  s += "  d.init((LDS unsigned char*)smem + wid * wave_bytes, lane, " + std::to_string(p.log2n) + ", " +
+       std::to_string(p.k) + ", llr, frame, bits, trace);\n";
+  s += "  run(d);\n  d.finish();\n}\n\n}  // namespace\n\n";
+  s += "extern \"C\" __global__ void __launch_bounds__(256) polar_unrolled(const " + std::string(chan) +
+       "* __restrict__ llr, int nframes, uint8_t* __restrict__ bits, int wave_bytes) {\n";
+  s += "  extern __shared__ __align__(16) unsigned char smem[];\n";
+  s += "  entry(llr, nframes, bits, nullptr, wave_bytes, smem);\n}\n\n";
+  s += "extern \"C\" __global__ void __launch_bounds__(256) polar_unrolled_trace(const " + std::string(chan) +
+       "* __restrict__ llr, int nframes, uint8_t* __restrict__ bits, " + chan +
+       "* __restrict__ trace, int wave_bytes) {\n";
+  s += "  extern __shared__ __align__(16) unsigned char smem[];\n";
+  s += "  entry(llr, nframes, bits, trace, wave_bytes, smem);\n}\n";
+  return s;
+}
+
+std::string unrolled_cache_path(const std::string& src) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  h = fnv1a(h, src.data(), src.size());
+  h = fnv1a(h, kOpcodesH, sizeof(kOpcodesH));
+  h = fnv1a(h, kDecodeOpsH, sizeof(kDecodeOpsH));
+  for (int i = 0; i < kNumOptions; ++i) h = fnv1a(h, kOptions[i], strlen(kOptions[i]) + 1);
+  int major = 0, minor = 0;
+  (void)hiprtcVersion(&major, &minor);
+  h = fnv1a(h, &major, sizeof major);
+  h = fnv1a(h, &minor, sizeof minor);
+  char name[40];
+  snprintf(name, sizeof name, "%016llx.hsaco", (unsigned long long)h);
+  return cache_dir() + "/" + name;
+}
+
+// Returns 0 and the code object, from the cache or freshly compiled (and
+// then stored), or -1 with the compiler log.
+int unrolled_code_object(const Plan& p, int llr_type, std::vector<char>& code, std::string& log) {
+  const std::string src = unrolled_source(p, llr_type);
+  const std::string path = unrolled_cache_path(src);
+  if (read_file(path, code)) return 0;
+  hiprtcProgram prog;
+  const char* headers[] = {kOpcodesH, kDecodeOpsH};
+  const char* names[] = {"opcodes.h", "decode_ops.h"};
+  if (hiprtcCreateProgram(&prog, src.c_str(), "polar_unrolled.hip", 2, headers, names) != HIPRTC_SUCCESS) {
+    log = "hiprtcCreateProgram failed";
+    return -1;
+  }
+  const hiprtcResult r = hiprtcCompileProgram(prog, kNumOptions, kOptions);
+  size_t log_size = 0;
+  if (hiprtcGetProgramLogSize(prog, &log_size) == HIPRTC_SUCCESS && log_size > 1) {
+    log.resize(log_size);
+    hiprtcGetProgramLog(prog, &log[0]);
+  }
+  if (r != HIPRTC_SUCCESS) {
+    hiprtcDestroyProgram(&prog);
+    return -1;
+  }
+  size_t size = 0;
+  hiprtcGetCodeSize(prog, &size);
+  code.resize(size);
+  hiprtcGetCode(prog, code.data());
+  hiprtcDestroyProgram(&prog);
+  if (size == 0) return -1;
+  const std::string dir = cache_dir();
+  mkdir(dir.c_str(), 0755);  // may exist; a failed store only costs a recompile later
+  (void)write_file_atomic(path, code);
+  return 0;
+}
+
+int unrolled_load(const std::vector<char>& code, UnrolledKernel& k) {
+  if (hipModuleLoadData(&k.module, code.data()) != hipSuccess) return -1;
+  if (hipModuleGetFunction(&k.fn, k.module, "polar_unrolled") != hipSuccess ||
+      hipModuleGetFunction(&k.fn_trace, k.module, "polar_unrolled_trace") != hipSuccess) {
+    (void)hipModuleUnload(k.module);
+    k = UnrolledKernel();
+    return -1;
+  }
+  return 0;
+}
+
+void unrolled_unload(UnrolledKernel& k) {
+  if (k.module) (void)hipModuleUnload(k.module);
+  k = UnrolledKernel();
+}
+
+int unrolled_launch(const UnrolledKernel& k, int log2n, int llr_type, const void* llr, int nframes, uint8_t* bits,
+                    void* trace, int waves_per_block, void* stream) {
+  int wb = wave_lds_bytes(log2n, llr_type == 1 ? 4 : 1);
+  const unsigned grid = (unsigned)((nframes + waves_per_block - 1) / waves_per_block);
+  const unsigned block = 64u * (unsigned)waves_per_block;
+  const unsigned lds = (unsigned)wb * (unsigned)waves_per_block;
+  hipError_t e;
+  if (trace) {
+    void* args[] = {(void*)&llr, (void*)&nframes, (void*)&bits, (void*)&trace, (void*)&wb};
+    e = hipModuleLaunchKernel(k.fn_trace, grid, 1, 1, block, 1, 1, lds, (hipStream_t)stream, args, nullptr);
+  } else {
+    void* args[] = {(void*)&llr, (void*)&nframes, (void*)&bits, (void*)&wb};
+    e = hipModuleLaunchKernel(k.fn, grid, 1, 1, block, 1, 1, lds, (hipStream_t)stream, args, nullptr);
+  }
+  return (int)e;
+}
+
+}  // namespace polar

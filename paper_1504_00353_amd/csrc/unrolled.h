@@ -1,0 +1,35 @@
+// Generated per-code (unrolled) decode kernels: source generation, the
+// on-disk code object cache, module loading and launch.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <string>
+#include <vector>
+
+#include "plan.h"
+
+namespace polar {
+
+struct UnrolledKernel {
+  hipModule_t module = nullptr;
+  hipFunction_t fn = nullptr;
+  hipFunction_t fn_trace = nullptr;
+};
+
+// HIP source of the two kernels (plain and tracing) for the plan's device
+// schedule and the LLR type (0 int8, 1 float).
+std::string unrolled_source(const Plan& p, int llr_type);
+
+// Code object of the plan's kernels from the cache, or compiled now and
+// stored.  0 on success; -1 with the compiler log otherwise.
+int unrolled_code_object(const Plan& p, int llr_type, std::vector<char>& code, std::string& log);
+
+// Loads a code object on the current device.  0 on success.
+int unrolled_load(const std::vector<char>& code, UnrolledKernel& k);
+void unrolled_unload(UnrolledKernel& k);
+
+// Launches the loaded kernel; returns the hipError_t of the launch.
+int unrolled_launch(const UnrolledKernel& k, int log2n, int llr_type, const void* llr, int nframes, uint8_t* bits,
+                    void* trace, int waves_per_block, void* stream);
+
+}  // namespace polar

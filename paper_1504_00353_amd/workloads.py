@@ -54,3 +54,12 @@ STRESS = dict(
     codes=[(32768, 29492, 4.0), (4096, 3686, 4.0)], ebn0_db=4.5, frames=262144)
 
 ALL = [SC_1024, FSSC_32K, FSSC_32K_F32, MIXED, SERVING, STRESS]
+
+# Further codes whose unrolled kernels are built ahead of time: the small
+# codes of the smoke run and of the unrolled-kernel parity tests.
+UNROLLED_EXTRA = [
+    (1024, 512, 2.5, "fastssc", "i8"),
+    (1024, 512, 2.5, "fastssc", "f32"),
+    (256, 128, 2.5, "sc", "i8"),
+    (4096, 3686, 4.0, "fastssc", "f32"),
+]

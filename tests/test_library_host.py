@@ -50,8 +50,34 @@ def test_invalid_arguments_are_rejected():
     assert L.polar_schedule(None, None, None, None, 0, None) == binding.EINVAL
     assert L.polar_encode(c.handle, None, 1, None) == binding.EINVAL
     assert L.polar_n(None) == 0 and L.polar_k(None) == 0
+    assert L.polar_set_kernel(c.handle, 2) == binding.EINVAL
+    assert L.polar_set_kernel(None, 0) == binding.EINVAL
+    assert L.polar_build_kernel(None) == binding.EINVAL
     L.polar_destroy(None)
     assert binding.lib().polar_strerror(binding.ESTATE) == b"invalid state"
+    assert binding.lib().polar_strerror(binding.ECOMPILE) == b"kernel compilation failed"
+
+
+def test_unrolled_kernel_builds_into_cache(tmp_path, monkeypatch):
+    """polar_build_kernel compiles a code's unrolled kernel on the host into
+    the cache directory; a second build is a cache hit; another code or
+    LLR type gets another code object."""
+    import time
+    monkeypatch.setenv("POLAR_KERNEL_CACHE", str(tmp_path))
+    fr = np.array([1, 1, 0, 0, 1, 0, 0, 0], np.uint8)
+    c = binding.Code(frozen=fr, prepare=False, kernel="unrolled")
+    c.build_kernel()
+    files = sorted(os.listdir(tmp_path))
+    assert len(files) == 1 and files[0].endswith(".hsaco")
+    blob = open(os.path.join(tmp_path, files[0]), "rb").read()
+    assert blob[:4] == b"\x7fELF" and b"polar_unrolled_trace" in blob and b"polar_unrolled" in blob
+    t0 = time.perf_counter()
+    c.build_kernel()
+    assert time.perf_counter() - t0 < 0.5
+    assert sorted(os.listdir(tmp_path)) == files
+    binding.Code(frozen=fr, llr="f32", prepare=False, kernel="unrolled").build_kernel()
+    binding.Code(frozen=fr, algo="sc", prepare=False, kernel="unrolled").build_kernel()
+    assert len(os.listdir(tmp_path)) == 3
 
 
 CODES = sorted({(n, k, d) for w in workloads.ALL for (n, k, d) in w["codes"]} | {(8, 5, 2.0), (64, 32, 2.5)})

@@ -96,9 +96,10 @@ def test_constructed_codes_channel_frames(n, k, d, llr):
     check_parity(code, fr, l, "fastssc", label="(%d,%d) %s" % (n, k, llr))
 
 
-def test_sc_1024_512_float32_full_workload():
+@pytest.mark.parametrize("kernel", ["schedule", "unrolled"])
+def test_sc_1024_512_float32_full_workload(kernel):
     """(1024,512), plain SC, float32, 10,000 frames at 2.5 dB."""
-    code = Code(1024, 512, 2.5, algo="sc", llr="f32")
+    code = Code(1024, 512, 2.5, algo="sc", llr="f32", kernel=kernel)
     fr = code.frozen()
     _, _, l = make_frames(fr, 1, 10000, 2.5, "f32")
     check_parity(code, fr, l, "sc", label="sc-1024")
@@ -110,20 +111,22 @@ def test_sc_1024_512_float32_full_workload():
     assert (np.abs(tr.astype(np.float64) - t64) <= 1e-5 * scale).all()
 
 
+@pytest.mark.parametrize("kernel", ["schedule", "unrolled"])
 @pytest.mark.parametrize("llr", ["i8", "f32"])
-def test_fastssc_32768_29492_full_workload(llr):
+def test_fastssc_32768_29492_full_workload(llr, kernel):
     """(32768,29492) Fast-SSC, 4,096 frames at 4.0 dB, every frame."""
-    code = Code(32768, 29492, 4.0, llr=llr)
+    code = Code(32768, 29492, 4.0, llr=llr, kernel=kernel)
     fr = code.frozen()
     _, _, l = make_frames(fr, 2, 4096, 4.0, llr)
     check_parity(code, fr, l, "fastssc", trace=True, label="32k " + llr)
 
 
+@pytest.mark.parametrize("kernel", ["schedule", "unrolled"])
 @pytest.mark.parametrize("n,k", [(4096, 3686), (32768, 29492)])
-def test_stress_launch_262144_frames_sampled(n, k):
+def test_stress_launch_262144_frames_sampled(n, k, kernel):
     """One launch of 262,144 frames (a pool of 2,048 distinct frames tiled);
     sampled frames against the oracle, and every tile identical."""
-    code = Code(n, k, 4.0, llr="i8")
+    code = Code(n, k, 4.0, llr="i8", kernel=kernel)
     fr = code.frozen()
     pool = 2048
     _, _, l = make_frames(fr, 5, pool, 4.5, "i8")
@@ -184,3 +187,37 @@ def test_zero_frames_is_noop():
     out = code.decode(t)
     torch.cuda.synchronize()
     assert out.shape == (0, 16)
+
+
+def _unrolled_specs():
+    from paper_1504_00353_amd import build
+    return build._kernel_specs()
+
+
+@pytest.mark.parametrize("spec", _unrolled_specs(), ids=lambda t: "%d_%d_%s_%s" % (t[0], t[1], t[3], t[4]))
+def test_unrolled_kernel_codes(spec):
+    """Every code with a prebuilt unrolled kernel: bits and leaf-LLR trace
+    against the oracle, and bits identical to the schedule kernel, on
+    channel frames plus extreme and tied LLRs."""
+    n, k, d, algo, llr = spec
+    code = Code(n, k, d, algo=algo, llr=llr, kernel="unrolled")
+    ref = Code(n, k, d, algo=algo, llr=llr, kernel="schedule")
+    fr = code.frozen()
+    frames = 96 if n >= 16384 else 300
+    _, _, l = make_frames(fr, 11, frames, d, llr)
+    rng = np.random.default_rng(n + k)
+    kind = "f32" if llr == "f32" else "i8"
+    l = np.concatenate([l, random_llrs(rng, 16, n, kind)] + ([random_llrs(rng, 16, n, "i8small")] if kind == "i8" else []))
+    check_parity(code, fr, l, algo, label="unrolled %s" % (spec,))
+    b1, _ = gpu_decode(code, l)
+    b0, _ = gpu_decode(ref, l)
+    assert np.array_equal(b0, b1)
+
+
+@pytest.mark.parametrize("frames", [1, 3, 4, 5, 65])
+def test_unrolled_ragged_frame_counts(frames):
+    """Frame counts that leave the last block partly empty."""
+    code = Code(1024, 512, 2.5, llr="i8", kernel="unrolled")
+    fr = code.frozen()
+    _, _, l = make_frames(fr, 12, frames, 2.5, "i8")
+    check_parity(code, fr, l, "fastssc", label="unrolled ragged %d" % frames)
