@@ -116,6 +116,11 @@ void polar_destroy(polar_code* code);
 polar_status polar_last_status(void);
 const char* polar_strerror(polar_status status);
 
+/* Details of the last failure on this thread, e.g. the compiler log after
+ * POLAR_ECOMPILE; "" when there are none.  Valid until the next call into
+ * the library on this thread. */
+const char* polar_last_message(void);
+
 int polar_n(const polar_code* code); /* 0 for NULL */
 int polar_k(const polar_code* code); /* 0 for NULL */
 

@@ -20,13 +20,16 @@ EXPORTS = [
     "polar_construct", "polar_construct_mask", "polar_configure", "polar_prepare", "polar_destroy",
     "polar_last_status", "polar_strerror", "polar_n", "polar_k", "polar_frozen_mask", "polar_schedule",
     "polar_encode", "polar_decode", "polar_decode_trace", "polar_set_kernel", "polar_build_kernel",
+    "polar_last_message",
 ]
 
 
 class PolarError(RuntimeError):
     def __init__(self, status, what):
         self.status = status
-        super().__init__("%s: %s" % (what, _lib().polar_strerror(status).decode()))
+        detail = _lib().polar_last_message().decode(errors="replace")
+        super().__init__("%s: %s%s" % (what, _lib().polar_strerror(status).decode(),
+                                       ("\n" + detail) if detail else ""))
 
 
 _L = None
@@ -53,6 +56,8 @@ def _lib():
         L.polar_last_status.argtypes = []
         L.polar_strerror.argtypes = [I]
         L.polar_strerror.restype = ctypes.c_char_p
+        L.polar_last_message.argtypes = []
+        L.polar_last_message.restype = ctypes.c_char_p
         L.polar_n.argtypes = [P]
         L.polar_k.argtypes = [P]
         L.polar_frozen_mask.argtypes = [P, P]

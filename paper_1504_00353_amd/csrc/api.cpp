@@ -32,9 +32,17 @@ struct polar_code {
 namespace {
 
 thread_local polar_status g_last = POLAR_OK;
+thread_local std::string g_message;
 
 polar_status set(polar_status s) {
   g_last = s;
+  if (s == POLAR_OK) g_message.clear();
+  return s;
+}
+
+polar_status set_msg(polar_status s, const std::string& msg) {
+  g_last = s;
+  g_message = msg;
   return s;
 }
 
@@ -135,7 +143,7 @@ polar_status polar_build_kernel(const polar_code* c) {
   try {
     std::vector<char> code;
     std::string log;
-    if (polar::unrolled_code_object(c->plan, c->llr_type, code, log) != 0) return set(POLAR_ECOMPILE);
+    if (polar::unrolled_code_object(c->plan, c->llr_type, code, log) != 0) return set_msg(POLAR_ECOMPILE, log);
   } catch (const std::bad_alloc&) {
     return set(POLAR_ENOMEM);
   }
@@ -159,7 +167,7 @@ polar_status polar_prepare(polar_code* c) {
     try {
       std::vector<char> code;
       std::string log;
-      if (polar::unrolled_code_object(c->plan, c->llr_type, code, log) != 0) return set(POLAR_ECOMPILE);
+      if (polar::unrolled_code_object(c->plan, c->llr_type, code, log) != 0) return set_msg(POLAR_ECOMPILE, log);
       if (polar::unrolled_load(code, c->unrolled) != 0) return set(POLAR_EDEVICE);
     } catch (const std::bad_alloc&) {
       return set(POLAR_ENOMEM);
@@ -196,6 +204,8 @@ void polar_destroy(polar_code* c) {
 }
 
 polar_status polar_last_status(void) { return g_last; }
+
+const char* polar_last_message(void) { return g_message.c_str(); }
 
 const char* polar_strerror(polar_status s) {
   switch (s) {

@@ -82,7 +82,17 @@ __device__ __forceinline__ float from_up(float x) {
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__builtin_amdgcn_ballot_w64(p); }
-__device__ __forceinline__ bool lane_pred(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+// Per lane: b if bit `lane` of the wave-uniform mask m is set, else a (one
+// v_cndmask with the mask as its SGPR-pair condition).
+__device__ __forceinline__ float select_lane(uint64_t m, float a, float b) {
+  // the mask is wave-uniform; readfirstlane tells the compiler so (and
+  // costs nothing when it already lives in scalar registers)
+  const uint64_t mu = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32) |
+                      (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)m);
+  float r;
+  asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(mu));
+  return r;
+}
 __device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ float rflf(float x) { return __uint_as_float(rfl(__float_as_uint(x))); }
 // Orders the wave's LDS traffic across lanes and keeps the compiler from
@@ -188,9 +198,6 @@ struct Dec {
   int words_out;              // 64-bit output words stored so far
   uint64_t pend_v;            // bits the last op wants appended ...
   int pend_n;                 // ... and how many (0: none)
-  int pend_bits;              // > 0: emit u = x G of this many beta bits at pend_p
-  int pend_p;                 // dword offset of those bits in the beta array
-  int pend_flags;             // 1: skip u_0 (SPC); 2: undo the transform afterwards
 
   __device__ __forceinline__ LDS unsigned char* stage(int s) const { return alpha + ((1 << s) - 128) * P::ELEM; }
 
@@ -213,41 +220,42 @@ struct Dec {
     }
   }
 
-  // u = x G over nbits (>= 128, power of two) of the beta array starting at
-  // dword p, in place.  Lane L holds dwords L, L+64, ...
-  __device__ __forceinline__ void transform_bits(int p, int nbits) {
-    const int words = nbits >> 5;
-    for (int w = lane; w < words; w += 64) beta[p + w] = transform32(beta[p + w]);
-    wave_sync();
-    for (int d = 1; d < words; d <<= 1) {
-      for (int w = lane; w < words; w += 64)
-        if ((w & d) == 0) beta[p + w] ^= beta[p + w + d];
-      wave_sync();
-    }
-  }
-
-  // Output work recorded by the last op (one copy of this code in the loop).
+  // Bits recorded by the last small leaf or repetition node (one copy of
+  // the append code in the interpreter loop).
   __device__ __forceinline__ void settle() {
     if (pend_n) {
       append(pend_v, pend_n);
       pend_n = 0;
     }
-    if (pend_bits) {
-      const int p = pend_p;
-      transform_bits(p, pend_bits);
-      const LDS u32x2* q = (const LDS u32x2*)(beta + p);
-      for (int t = 0; t < pend_bits / 64; ++t) {
-        const u32x2 v2 = q[t];  // the same address in every lane: a broadcast
-        const uint64_t v = ((uint64_t)rfl(v2[1]) << 32) | rfl(v2[0]);
-        if (t == 0 && (pend_flags & 1))
-          append(v >> 1, 63);
-        else
-          append(v, 64);
-      }
-      wave_sync();
-      if (pend_flags & 2) transform_bits(p, pend_bits);
-      pend_bits = 0;
+  }
+
+  // Stores 64-bit output word w (index widx in the row), one byte per store
+  // (rows are byte aligned).
+  __device__ __forceinline__ void store_word(int widx, uint64_t w) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int idx = 8 * widx + k;
+      if (idx < row_bytes) row[idx] = (uint8_t)(w >> (8 * k));
     }
+  }
+
+  // u bits [b, b + 64) of a node whose u is staged as nw 32-bit words at st
+  // (zero past the node).
+  __device__ __forceinline__ uint64_t staged_bits(const LDS uint32_t* st, int nw, int b) const {
+    const int q = b >> 5, r = b & 31;
+    const uint32_t d0 = q < nw ? st[q] : 0u;
+    const uint32_t d1 = q + 1 < nw ? st[q + 1] : 0u;
+    const uint32_t d2 = q + 2 < nw ? st[q + 2] : 0u;
+    const uint64_t lo = (uint64_t)d0 | ((uint64_t)d1 << 32);
+    return r ? (lo >> r) | ((uint64_t)d2 << (64 - r)) : lo;
+  }
+
+  // Output-stream word t after appending u bits [skip, 32 nw) of a staged
+  // node: the stream is the fill bits held in acc, then those u bits.
+  __device__ __forceinline__ uint64_t stream_word(const LDS uint32_t* st, int nw, int t, int skip) const {
+    const int b = 64 * t - fill + skip;
+    if (b < skip) return acc | (staged_bits(st, nw, skip) << fill);  // t == 0, fill > 0
+    return staged_bits(st, nw, b);
   }
 
   // ------------------------------------------------- nodes of size <= 64
@@ -259,8 +267,7 @@ struct Dec {
     if (code == DOP_F) {
       a[S - 1] = fmin_sum(x, y);
     } else if (code == DOP_G) {
-      const bool neg = lane_pred(win >> (o & 63));
-      a[S - 1] = P::clamp32(y + (neg ? -x : x));
+      a[S - 1] = P::clamp32(y + select_lane(win >> (o & 63), x, -x));
     } else {
       a[S - 1] = P::clamp32(y + x);
     }
@@ -367,7 +374,7 @@ struct Dec {
     if (code == DOP_F)
       a[6] = fmin_sum(x, y);
     else if (code == DOP_G)
-      a[6] = P::clamp32(y + (lane_pred(win) ? -x : x));  // beta of the left size-64 child
+      a[6] = P::clamp32(y + select_lane(win, x, -x));  // beta of the left size-64 child
     else
       a[6] = P::clamp32(y + x);
   }
@@ -577,56 +584,203 @@ struct Dec {
       pend_n = 1;
       return;
     }
-    // Rate-1 / SPC: hard decisions, 32 elements (one beta word) per lane
-    int parity = 0;
-    float best = 3.0e38f;
-    int best_i = 0x7fffffff;
-    for (int j = lane; j < (nv >> 5); j += 64) {
-      uint32_t d = 0;
+    switch (S) {
+      case 7: leaf_r1spc<7>(code, o); break;
+      case 8: leaf_r1spc<8>(code, o); break;
+      case 9: leaf_r1spc<9>(code, o); break;
+      case 10: leaf_r1spc<10>(code, o); break;
+      case 11: leaf_r1spc<11>(code, o); break;
+      case 12: leaf_r1spc<12>(code, o); break;
+      case 13: leaf_r1spc<13>(code, o); break;
+      case 14: leaf_r1spc<14>(code, o); break;
+      default: leaf_r1spc<15>(code, o); break;
+    }
+  }
+
+  // Hard decisions (eq. (4)) of elements i0 .. i0+31 of the input of a leaf
+  // at stage S: bit k is 1 iff element i0 + k is negative.
+  template <int S, bool CH>
+  __device__ __forceinline__ uint32_t hd32(int i0) {
+    uint32_t d = 0;
+    if constexpr (P::ELEM == 1) {
+      u32x4 q0, q1;
+      if constexpr (CH) {
+        q0 = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(chr, i0, 0, 0));
+        q1 = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(chr, i0 + 16, 0, 0));
+      } else {
+        q0 = *(const LDS u32x4*)(stage(S) + i0);
+        q1 = *(const LDS u32x4*)(stage(S) + i0 + 16);
+      }
+      // the sign bit of each byte, gathered four at a time by a dot product
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        d |= __builtin_amdgcn_udot4((q0[k] >> 7) & 0x01010101u, 0x08040201u, 0u, false) << (4 * k);
+        d |= __builtin_amdgcn_udot4((q1[k] >> 7) & 0x01010101u, 0x08040201u, 0u, false) << (16 + 4 * k);
+      }
+    } else {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        float v[4];
-        leaf_quad(S, 32 * j + 4 * q, v);
+        u32x4 v;
+        if constexpr (CH)
+          v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(chr, 4 * (i0 + 4 * q), 0, 0));
+        else
+          v = *(const LDS u32x4*)(stage(S) + 4 * (i0 + 4 * q));
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int i = 32 * j + 4 * q + k;
-          if (tr) tr[o + i] = P::to_chan(v[k]);
-          d |= (v[k] < 0.0f ? 1u : 0u) << (4 * q + k);
-          const float mg = fabsf(v[k]);
-          if (mg < best) {
-            best = mg;
-            best_i = i;
-          }
-        }
+        for (int k = 0; k < 4; ++k) d |= (__uint_as_float(v[k]) < 0.0f ? 1u : 0u) << (4 * q + k);
       }
-      bw[j] = d;
-      parity ^= __popc(d) & 1;
     }
-    if (code == DOP_SPC && (__popcll(ballot(parity != 0)) & 1)) {
-      float v = best;
-      v = fminf(v, __shfl_xor(v, 32, 64));
-      v = fminf(v, __shfl_xor(v, 16, 64));
-      v = fminf(v, __shfl_xor(v, 8, 64));
-      v = fminf(v, __shfl_xor(v, 4, 64));
-      v = fminf(v, __shfl_xor(v, 2, 64));
-      v = fminf(v, __shfl_xor(v, 1, 64));
-      int idx = (best == v) ? best_i : 0x7fffffff;
-      idx = min(idx, __shfl_xor(idx, 32, 64));
-      idx = min(idx, __shfl_xor(idx, 16, 64));
-      idx = min(idx, __shfl_xor(idx, 8, 64));
-      idx = min(idx, __shfl_xor(idx, 4, 64));
-      idx = min(idx, __shfl_xor(idx, 2, 64));
-      idx = min(idx, __shfl_xor(idx, 1, 64));
-      idx = (int)rfl((uint32_t)idx);
+    return d;
+  }
+
+  // Element i of the input of a leaf at stage S (int8: -128 read as -127).
+  template <int S>
+  __device__ __forceinline__ float leaf_elem(int i) {
+    if constexpr (P::ELEM == 1) {
+      int x;
+      if (S == log2n)
+        x = (int)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(chr, i, 0, 0);
+      else
+        x = (int)*(const LDS int8_t*)(stage(S) + i);
+      return (float)(x < -127 ? -127 : x);
+    } else {
+      if (S == log2n) return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(chr, 4 * i, 0, 0));
+      return ((const LDS float*)stage(S))[i];
+    }
+  }
+
+  // SPC correction index (Listing 2): the lowest index among the elements of
+  // least magnitude.  Wave-uniform result.
+  template <int S>
+  __device__ __forceinline__ int spc_argmin() {
+    constexpr int NV = 1 << S;
+    float best = 3.0e38f;
+    int bi = 0x7fffffff;
+#pragma unroll 8
+    for (int i = lane; i < NV; i += 64) {
+      const float m = fabsf(leaf_elem<S>(i));
+      if (m < best) {  // indices grow, so the first of equal values stays
+        best = m;
+        bi = i;
+      }
+    }
+    float v = best;
+    v = fminf(v, __shfl_xor(v, 32, 64));
+    v = fminf(v, __shfl_xor(v, 16, 64));
+    v = fminf(v, __shfl_xor(v, 8, 64));
+    v = fminf(v, __shfl_xor(v, 4, 64));
+    v = fminf(v, __shfl_xor(v, 2, 64));
+    v = fminf(v, __shfl_xor(v, 1, 64));
+    int idx = best == v ? bi : 0x7fffffff;
+    idx = min(idx, __shfl_xor(idx, 32, 64));
+    idx = min(idx, __shfl_xor(idx, 16, 64));
+    idx = min(idx, __shfl_xor(idx, 8, 64));
+    idx = min(idx, __shfl_xor(idx, 4, 64));
+    idx = min(idx, __shfl_xor(idx, 2, 64));
+    idx = min(idx, __shfl_xor(idx, 1, 64));
+    return (int)rfl((uint32_t)idx);
+  }
+
+  // The node's beta words from hard decisions: lane j gets words j, j+64, ...
+  template <int S, bool CH, int PER>
+  __device__ __forceinline__ void hd_words(uint32_t* wd) {
+    constexpr int NW = 1 << (S - 5);
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int j = lane + 64 * m;
+      wd[m] = 0u;
+      if (NW >= 64 || j < NW) wd[m] = hd32<S, CH>(32 * j);
+    }
+  }
+
+  // Words w (bit D of the lane index clear) ^= word w + D, D < 64 words.
+  template <int D, int PER>
+  __device__ __forceinline__ void xor_up_lanes(uint32_t* wd) {
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const uint32_t p = from_up<D>(wd[m]);
+      if ((lane & D) == 0) wd[m] ^= p;
+    }
+  }
+
+  // Rate-1 or SPC leaf of size 2^S >= 128.  Lane j holds beta words
+  // j, j + 64, ... (32 elements each) in registers: hard decisions, the SPC
+  // parity check and correction (Sec. II-E), the words to the beta array,
+  // then u = beta G in registers and the information bits (all of u, or u
+  // without u_0 for SPC) to the output, 64-bit words in parallel.
+  template <int S>
+  __device__ __forceinline__ void leaf_r1spc(uint32_t code, int o) {
+    constexpr int NV = 1 << S;
+    constexpr int NW = NV >> 5;                 // 32-bit words: 4 .. 1024
+    constexpr int PER = NW >= 64 ? NW / 64 : 1; // words per lane
+    LDS uint32_t* bw = beta + (o >> 5);
+    uint32_t wd[PER];
+    if (S == log2n)
+      hd_words<S, true, PER>(wd);
+    else
+      hd_words<S, false, PER>(wd);
+    int par = 0;
+#pragma unroll
+    for (int m = 0; m < PER; ++m) par ^= __popc(wd[m]);
+    if (tr)
+      for (int i = lane; i < NV; i += 64) tr[o + i] = P::to_chan(leaf_elem<S>(i));
+    if (code == DOP_SPC && (__popcll(ballot((par & 1) != 0)) & 1)) {
+      const int idx = spc_argmin<S>();
+      const int jw = idx >> 5;
+      if ((jw & 63) == lane) {
+#pragma unroll
+        for (int m = 0; m < PER; ++m)
+          if (m == (jw >> 6)) wd[m] ^= 1u << (idx & 31);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int j = lane + 64 * m;
+      if (NW >= 64 || j < NW) bw[j] = wd[m];
+    }
+    // u = beta G_NV: the levels inside a word, across lanes, across registers
+#pragma unroll
+    for (int m = 0; m < PER; ++m) wd[m] = transform32(wd[m]);
+    if constexpr (NW > 1) xor_up_lanes<1, PER>(wd);
+    if constexpr (NW > 2) xor_up_lanes<2, PER>(wd);
+    if constexpr (NW > 4) xor_up_lanes<4, PER>(wd);
+    if constexpr (NW > 8) xor_up_lanes<8, PER>(wd);
+    if constexpr (NW > 16) xor_up_lanes<16, PER>(wd);
+    if constexpr (NW > 32) xor_up_lanes<32, PER>(wd);
+#pragma unroll
+    for (int dm = 1; dm < PER; dm <<= 1)
+#pragma unroll
+      for (int m = 0; m < PER; ++m)
+        if ((m & dm) == 0) wd[m] ^= wd[m + dm];
+    const int skip = code == DOP_SPC ? 1 : 0;
+    if constexpr (NW <= 4) {
+      // 128 bits: through the scalar accumulator
+      const uint64_t v0 = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)wd[0], 0) |
+                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)wd[0], 1) << 32);
+      const uint64_t v1 = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)wd[0], 2) |
+                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)wd[0], 3) << 32);
+      if (skip)
+        append(v0 >> 1, 63);
+      else
+        append(v0, 64);
+      append(v1, 64);
+    } else {
+      // stage u in the alpha buffer of stage S-1 (dead at a leaf, and at
+      // least NV/8 bytes), then every lane builds whole output words
+      LDS uint32_t* st = (LDS uint32_t*)stage(S - 1);
+#pragma unroll
+      for (int m = 0; m < PER; ++m)
+        if (NW >= 64 || lane < NW) st[lane + 64 * m] = wd[m];
       wave_sync();
-      if (lane == 0) bw[idx >> 5] ^= 1u << (idx & 31);
+      const int total = fill + NV - skip;
+      const int T = total >> 6;
+      for (int t = lane; t < T; t += 64) store_word(words_out + t, stream_word(st, NW, t, skip));
+      const int nf = total & 63;
+      uint64_t rest = 0;
+      if (nf) rest = stream_word(st, NW, T, skip) & low_mask(nf);  // same words in every lane
+      acc = ((uint64_t)rfl((uint32_t)(rest >> 32)) << 32) | rfl((uint32_t)rest);
+      fill = nf;
+      words_out += T;
     }
-    wave_sync();
-    // information bits: u = beta G over the node, computed in place and
-    // undone afterwards unless this is the root
-    pend_bits = nv;
-    pend_p = o >> 5;
-    pend_flags = (code == DOP_SPC ? 1 : 0) | (S < log2n ? 2 : 0);
   }
 
   // Halving-tree repetition sum of a float leaf: the levels above 64 run in
@@ -760,8 +914,10 @@ struct Dec {
       }
     } else if constexpr (code <= DOP_CR0) {
       big_combine(code, S, o);
-    } else {
+    } else if constexpr (code == DOP_REP) {
       big_leaf(code, S, o);
+    } else {
+      leaf_r1spc<S>(code, o);
     }
     if constexpr (code >= DOP_R1 && code <= DOP_SPC) settle();
     wave_sync();
@@ -787,9 +943,6 @@ struct Dec {
     words_out = 0;
     pend_v = 0;
     pend_n = 0;
-    pend_bits = 0;
-    pend_p = 0;
-    pend_flags = 0;
 #pragma unroll
     for (int s = 0; s < 7; ++s) a[s] = 0.0f;
     // g sign table: entry e (4 beta bits) -> two +-1 pairs

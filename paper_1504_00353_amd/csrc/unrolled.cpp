@@ -35,7 +35,7 @@ namespace polar {
 
 namespace {
 
-const char* const kOptions[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+const char* const kOptions[] = {"--offload-arch=gfx950", "-mwavefrontsize64", "-O3", "-std=c++17", "-ffp-contract=off",
                                 "-fno-honor-nans", "-fno-honor-infinities", "-Xclang", "-target-feature",
                                 "-Xclang", "-packed-fp32-ops"};
 constexpr int kNumOptions = sizeof(kOptions) / sizeof(kOptions[0]);

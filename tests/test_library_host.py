@@ -123,3 +123,25 @@ def test_encoder_matches_oracle(n, k, d):
     x = c.encode(synth.pack_bits(bits))
     expect = oracle.encode(synth.scatter_info(bits, fr))
     assert np.array_equal(synth.unpack_bits(x, n), expect)
+
+
+def test_unrolled_kernel_builds_with_torch_loaded(tmp_path):
+    """In a process that imported torch first, the HIP run-time compiler
+    runs on the compiler library torch brought along; the generated source
+    must compile there too (the kernel cache may be filled from such a
+    process)."""
+    import subprocess
+    import sys
+    code = (
+        "import torch, sys, numpy as np\n"
+        "sys.path.insert(0, %r)\n"
+        "from paper_1504_00353_amd import binding\n"
+        "fr = np.array([1, 1, 0, 0, 1, 0, 0, 0], np.uint8)\n"
+        "for llr in ('i8', 'f32'):\n"
+        "    binding.Code(frozen=fr, llr=llr, prepare=False, kernel='unrolled').build_kernel()\n"
+        "binding.Code(256, 128, 2.5, prepare=False, kernel='unrolled').build_kernel()\n"
+        "print('built')\n" % ROOT)
+    env = dict(os.environ, POLAR_KERNEL_CACHE=str(tmp_path))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0 and "built" in r.stdout, r.stdout + r.stderr
+    assert len(os.listdir(tmp_path)) == 3
