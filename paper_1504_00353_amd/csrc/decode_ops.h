@@ -663,6 +663,11 @@ struct Dec {
         bi = i;
       }
     }
+    return argmin_reduce(best, bi);
+  }
+
+  // Wave-wide (minimum, lowest index attaining it) from per-lane candidates.
+  __device__ __forceinline__ int argmin_reduce(float best, int bi) {
     float v = best;
     v = fminf(v, __shfl_xor(v, 32, 64));
     v = fminf(v, __shfl_xor(v, 16, 64));
@@ -707,8 +712,10 @@ struct Dec {
   // parity check and correction (Sec. II-E), the words to the beta array,
   // then u = beta G in registers and the information bits (all of u, or u
   // without u_0 for SPC) to the output, 64-bit words in parallel.
+  // st_stage: an LDS alpha stage free at this leaf, of at least 2^S / 8
+  // bytes, used as scratch (default: the stage below the leaf).
   template <int S>
-  __device__ __forceinline__ void leaf_r1spc(uint32_t code, int o) {
+  __device__ __forceinline__ void leaf_r1spc(uint32_t code, int o, int st_stage = S - 1) {
     constexpr int NV = 1 << S;
     constexpr int NW = NV >> 5;                 // 32-bit words: 4 .. 1024
     constexpr int PER = NW >= 64 ? NW / 64 : 1; // words per lane
@@ -737,6 +744,17 @@ struct Dec {
       const int j = lane + 64 * m;
       if (NW >= 64 || j < NW) bw[j] = wd[m];
     }
+    finish_leaf<S, PER>(wd, code, (LDS uint32_t*)stage(st_stage));
+  }
+
+  // u = beta G of a Rate-1 or SPC leaf of size 2^S from its beta words in
+  // registers (lane j holds words j, j + 64, ...), and its information bits
+  // (all of u, or u without u_0 for SPC) to the output.  st: LDS scratch of
+  // at least 2^S / 8 bytes.
+  template <int S, int PER>
+  __device__ __forceinline__ void finish_leaf(uint32_t* wd, uint32_t code, LDS uint32_t* st) {
+    constexpr int NV = 1 << S;
+    constexpr int NW = NV >> 5;
     // u = beta G_NV: the levels inside a word, across lanes, across registers
 #pragma unroll
     for (int m = 0; m < PER; ++m) wd[m] = transform32(wd[m]);
@@ -764,9 +782,7 @@ struct Dec {
         append(v0, 64);
       append(v1, 64);
     } else {
-      // stage u in the alpha buffer of stage S-1 (dead at a leaf, and at
-      // least NV/8 bytes), then every lane builds whole output words
-      LDS uint32_t* st = (LDS uint32_t*)stage(S - 1);
+      // stage u in st, then every lane builds whole output words
 #pragma unroll
       for (int m = 0; m < PER; ++m)
         if (NW >= 64 || lane < NW) st[lane + 64 * m] = wd[m];
@@ -887,52 +903,16 @@ struct Dec {
     wave_sync();
   }
 
-  // The same step with the op word W and the code length 2^L2N known at
-  // compile time (generated kernels): only the code of this one op is
-  // instantiated, which keeps compile times of long schedules short.
-  template <uint32_t W, int L2N>
-  __device__ __forceinline__ void step_c() {
-    constexpr uint32_t code = W & 0xffu;
-    constexpr int S = (int)((W >> 8) & 0xffu);
-    constexpr int o = (int)(W >> 16);
-    if constexpr (S <= kRegStages) {
-      if constexpr (code <= DOP_G0R)
-        small_fg<S>(code, o);
-      else if constexpr (code <= DOP_CR0)
-        small_combine(code, S, o);
-      else if constexpr (code == DOP_FLUSH)
-        flush(o);
-      else
-        small_leaf<S>(code, o);
-    } else if constexpr (code <= DOP_G0R) {
-      if constexpr (S == 7) {
-        fg7(code);
-      } else if constexpr (P::ELEM == 1) {
-        i8_fg<(S >= 12 ? 16 : 4), S == L2N, code>(S, o);
-      } else {
-        f32_fg<S == L2N, code>(S, o);
-      }
-    } else if constexpr (code <= DOP_CR0) {
-      big_combine(code, S, o);
-    } else if constexpr (code == DOP_REP) {
-      big_leaf(code, S, o);
-    } else {
-      leaf_r1spc<S>(code, o);
-    }
-    if constexpr (code >= DOP_R1 && code <= DOP_SPC) settle();
-    wave_sync();
-  }
-
   // Sets up the decoder of frame `frame` in the LDS slot at `base`
-  // (wave_lds_bytes(log2n, elem) bytes).
+  // (wave_lds_bytes(log2n, elem, nreg) bytes).
   __device__ __forceinline__ void init(LDS unsigned char* base, int lane_, int log2n_, int kbits,
-                                       const Chan* llr, int frame, uint8_t* bits, Chan* trace) {
+                                       const Chan* llr, int frame, uint8_t* bits, Chan* trace, int nreg = 0) {
     const int n = 1 << log2n_;
     lane = lane_;
     log2n = log2n_;
     lut = (LDS uint32_t*)base;
     alpha = base + 128;
-    beta = (LDS uint32_t*)(base + 128 + lds_align16(log2n_ > 7 ? (n - 128) * P::ELEM : 0));
+    beta = (LDS uint32_t*)(base + 128 + lds_align16(alpha_lds_bytes(log2n_, P::ELEM, nreg)));
     chr = __builtin_amdgcn_make_buffer_rsrc((void*)(llr + (size_t)frame * n), 0, n * (int)sizeof(Chan), 0x00020000);
     tr = trace ? trace + (size_t)frame * n : nullptr;
     row_bytes = (kbits + 7) / 8;
@@ -974,6 +954,373 @@ struct Dec {
   // stores the last, partial output word
   __device__ __forceinline__ void finish() {
     if (fill > 0) emit(acc);
+  }
+};
+
+
+// ---------------------------------------------------------------------------
+// Decoder of the generated per-code kernels: every op word and the code
+// length 2^L2N are compile-time constants, so each op is instantiated for
+// its own stage and offset (Sec. III-B.4).  int8 codes may keep their NREG
+// top alpha stages (L2N-1 down to L2N-NREG, each >= 2^11 LLRs) in registers
+// instead of LDS, which cuts a frame's LDS footprint (N = 32768: 36.9 KB ->
+// 12.3 KB) so that more frames share a compute unit.  Register stages use
+// the chunked layout of the wide F/G ops: LLR e of stage s sits in lane
+// (e >> 4) & 63, register 4 (e >> 10) + ((e >> 2) & 3), byte e & 3, so the
+// pair e, e + 2^(s-1) of f and g is always lane-local.
+// ---------------------------------------------------------------------------
+template <int L2N, int NREG>
+struct RegStages {
+  static constexpr bool has(int s) { return NREG > 0 && s <= L2N - 1 && s >= L2N - NREG; }
+  // first register of stage s: stage L2N-1 first, then the next lower
+  static constexpr int base(int s) {
+    int b = 0;
+    for (int t = L2N - 1; t > s; --t) b += (1 << t) >> 8;
+    return b;
+  }
+  static constexpr int total() { return NREG > 0 ? base(L2N - NREG - 1) : 1; }
+};
+
+template <class P, int L2N, int NREG>
+struct DecU : Dec<P> {
+  typedef Dec<P> B;
+  typedef RegStages<L2N, NREG> R;
+  static_assert(NREG == 0 || (P::ELEM == 1 && L2N - NREG >= 11), "register stages: int8, >= 2^11 LLRs");
+  uint32_t rs[R::total()];
+
+  // highest alpha stage in LDS: scratch for leaves at register stages
+  static constexpr int kTopLds = L2N - NREG - 1;
+
+  // Gives the registers of stage S new names before an op reads them, so
+  // that no unpacked copies made by an earlier op on the same values stay
+  // alive until a later one (f and g read the same LLRs, and the compiler
+  // would otherwise share the unpacking between them).
+  template <int S>
+  __device__ __forceinline__ void launder() {
+#pragma unroll
+    for (int i = 0; i < ((1 << S) >> 8); ++i) asm volatile("" : "+v"(rs[R::base(S) + i]));
+  }
+
+  // ------------------------------------------------ wide F / G (int8)
+  // One 32-bit word (4 LLRs) of f, g or g_0R; b4: the 4 beta_l bits (g).
+  template <uint32_t CODE, bool CH>
+  __device__ __forceinline__ uint32_t fg_word(uint32_t A, uint32_t Bw, uint32_t b4) const {
+    s2 al = unpack_lo(A), ah = unpack_hi(A), bl = unpack_lo(Bw), bh = unpack_hi(Bw);
+    if constexpr (CH) {
+      al = chanx(al);
+      ah = chanx(ah);
+      bl = chanx(bl);
+      bh = chanx(bh);
+    }
+    s2 rl, rh;
+    if constexpr (CODE == DOP_F) {
+      rl = fx(al, bl);
+      rh = fx(ah, bh);
+    } else if constexpr (CODE == DOP_G) {
+      const u32x2 sg = *(const LDS u32x2*)(this->lut + 2 * b4);
+      rl = gx(al, bl, as_s2(sg[0]));
+      rh = gx(ah, bh, as_s2(sg[1]));
+    } else {
+      rl = g0x(al, bl);
+      rh = g0x(ah, bh);
+    }
+    return pack4(rl, rh);
+  }
+
+  // f / g / g_0R of a node at stage S (8 <= S <= L2N) into stage S-1.  A lane
+  // works on CB contiguous bytes of each half; batches of U iterations have
+  // all their loads in flight before any arithmetic.  Sources: the channel
+  // row, LDS or register stages; destinations: LDS or register stages.
+  template <int S, uint32_t CODE>
+  __device__ __forceinline__ void fg_i8(int o) {
+    constexpr int H = 1 << (S - 1);
+    constexpr bool CH = S == L2N;
+    constexpr bool SREG = R::has(S), DREG = R::has(S - 1);
+    constexpr int CB = S >= 11 ? 16 : (S == 10 ? 8 : 4);
+    constexpr int NW = CB / 4;
+    constexpr int PERIT = 64 * CB;
+    constexpr int IT = H >= PERIT ? H / PERIT : 1;
+    constexpr int U = IT < 8 ? IT : 8;
+    static_assert(!(SREG || DREG) || CB == 16, "register stages use 16-byte chunks");
+    const int lane = this->lane;
+    const LDS unsigned char* in = this->stage(S);
+    LDS unsigned char* out = this->stage(S - 1);
+    if constexpr (SREG) launder<S>();
+#pragma unroll
+    for (int b0 = 0; b0 < IT; b0 += U) {
+      uint32_t A[U][NW], Bv[U][NW], bb[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int it = b0 + u;
+        const int i0 = it * PERIT + lane * CB;
+        bb[u] = 0;
+        if (H >= PERIT || i0 < H) {
+          if constexpr (SREG) {
+#pragma unroll
+            for (int k = 0; k < NW; ++k) {
+              A[u][k] = rs[R::base(S) + 4 * it + k];
+              Bv[u][k] = rs[R::base(S) + 4 * (it + IT) + k];
+            }
+          } else if constexpr (CH && CB == 16) {
+            // the lane part of the offset in a register, the constant part
+            // as the scalar offset (no per-iteration address registers)
+            const u32x4 va =
+                __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(this->chr, lane * CB, it * PERIT, 0));
+            const u32x4 vb = __builtin_bit_cast(
+                u32x4, __builtin_amdgcn_raw_buffer_load_b128(this->chr, lane * CB, it * PERIT + H, 0));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              A[u][k] = va[k];
+              Bv[u][k] = vb[k];
+            }
+          } else if constexpr (CH && CB == 8) {
+            const u32x2 va =
+                __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(this->chr, lane * CB, it * PERIT, 0));
+            const u32x2 vb = __builtin_bit_cast(
+                u32x2, __builtin_amdgcn_raw_buffer_load_b64(this->chr, lane * CB, it * PERIT + H, 0));
+            A[u][0] = va[0];
+            A[u][1] = va[1];
+            Bv[u][0] = vb[0];
+            Bv[u][1] = vb[1];
+          } else if constexpr (CH) {
+            A[u][0] = __builtin_amdgcn_raw_buffer_load_b32(this->chr, lane * CB, it * PERIT, 0);
+            Bv[u][0] = __builtin_amdgcn_raw_buffer_load_b32(this->chr, lane * CB, it * PERIT + H, 0);
+          } else if constexpr (CB == 16) {
+            const u32x4 va = *(const LDS u32x4*)(in + i0);
+            const u32x4 vb = *(const LDS u32x4*)(in + i0 + H);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              A[u][k] = va[k];
+              Bv[u][k] = vb[k];
+            }
+          } else if constexpr (CB == 8) {
+            const u32x2 va = *(const LDS u32x2*)(in + i0);
+            const u32x2 vb = *(const LDS u32x2*)(in + i0 + H);
+            A[u][0] = va[0];
+            A[u][1] = va[1];
+            Bv[u][0] = vb[0];
+            Bv[u][1] = vb[1];
+          } else {
+            A[u][0] = *(const LDS uint32_t*)(in + i0);
+            Bv[u][0] = *(const LDS uint32_t*)(in + i0 + H);
+          }
+          if constexpr (CODE == DOP_G) bb[u] = this->beta[(o + i0) >> 5] >> ((o + i0) & 31);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int it = b0 + u;
+        const int i0 = it * PERIT + lane * CB;
+        if (H >= PERIT || i0 < H) {
+          uint32_t Rw[NW];
+#pragma unroll
+          for (int k = 0; k < NW; ++k) Rw[k] = fg_word<CODE, CH>(A[u][k], Bv[u][k], (bb[u] >> (4 * k)) & 15u);
+          if constexpr (DREG) {
+#pragma unroll
+            for (int k = 0; k < NW; ++k) rs[R::base(S - 1) + 4 * it + k] = Rw[k];
+          } else if constexpr (CB == 16) {
+            *(LDS u32x4*)(out + i0) = (u32x4){Rw[0], Rw[1], Rw[2], Rw[3]};
+          } else if constexpr (CB == 8) {
+            *(LDS u32x2*)(out + i0) = (u32x2){Rw[0], Rw[1]};
+          } else {
+            *(LDS uint32_t*)(out + i0) = Rw[0];
+          }
+        }
+      }
+    }
+  }
+
+  // ------------------------------------------------ wide F / G (float)
+  template <int S, uint32_t CODE>
+  __device__ __forceinline__ void fg_f32(int o) {
+    constexpr int H = 1 << (S - 1);
+    constexpr bool CH = S == L2N;
+    constexpr int PERIT = 256;  // 4 floats per lane
+    constexpr int IT = H >= PERIT ? H / PERIT : 1;
+    constexpr int U = IT < 8 ? IT : 8;
+    const int lane = this->lane;
+    const LDS float* in = (const LDS float*)this->stage(S);
+    LDS float* out = (LDS float*)this->stage(S - 1);
+#pragma unroll
+    for (int b0 = 0; b0 < IT; b0 += U) {
+      u32x4 va[U], vb[U];
+      uint32_t bb[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i0 = (b0 + u) * PERIT + lane * 4;
+        bb[u] = 0;
+        if (H >= PERIT || i0 < H) {
+          if constexpr (CH) {
+            va[u] = __builtin_bit_cast(
+                u32x4, __builtin_amdgcn_raw_buffer_load_b128(this->chr, 16 * lane, 4 * (b0 + u) * PERIT, 0));
+            vb[u] = __builtin_bit_cast(
+                u32x4, __builtin_amdgcn_raw_buffer_load_b128(this->chr, 16 * lane, 4 * ((b0 + u) * PERIT + H), 0));
+          } else {
+            va[u] = *(const LDS u32x4*)(in + i0);
+            vb[u] = *(const LDS u32x4*)(in + i0 + H);
+          }
+          if constexpr (CODE == DOP_G) bb[u] = this->beta[(o + i0) >> 5] >> ((o + i0) & 31);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i0 = (b0 + u) * PERIT + lane * 4;
+        if (H >= PERIT || i0 < H) {
+          float Rv[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const float a = __uint_as_float(va[u][k]), b = __uint_as_float(vb[u][k]);
+            if constexpr (CODE == DOP_F)
+              Rv[k] = fmin_sum(a, b);
+            else if constexpr (CODE == DOP_G)  // b + (-a) is exactly b - a
+              Rv[k] = __fadd_rn(b, __uint_as_float(va[u][k] ^ ((bb[u] << (31 - k)) & 0x80000000u)));
+            else
+              Rv[k] = __fadd_rn(b, a);
+          }
+          *(LDS u32x4*)(out + i0) = (u32x4){__float_as_uint(Rv[0]), __float_as_uint(Rv[1]), __float_as_uint(Rv[2]),
+                                            __float_as_uint(Rv[3])};
+        }
+      }
+    }
+  }
+
+  // ------------------------------------------ leaves at register stages
+  // 16 hard decisions of lane chunk `it` of register stage S.
+  template <int S>
+  __device__ __forceinline__ uint32_t reg_hd16(int it) const {
+    uint32_t d = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      d |= __builtin_amdgcn_udot4((rs[R::base(S) + 4 * it + k] >> 7) & 0x01010101u, 0x08040201u, 0u, false)
+           << (4 * k);
+    return d;
+  }
+
+  template <int S>
+  __device__ __forceinline__ int reg_elem(int it, int k, int b) const {
+    const int x = (int)(int8_t)(rs[R::base(S) + 4 * it + k] >> (8 * b));
+    return x < -127 ? -127 : x;
+  }
+
+  // Rate-1, repetition or SPC leaf whose LLRs are a register stage S.
+  template <int S>
+  __device__ __forceinline__ void leaf_reg(uint32_t code, int o) {
+    constexpr int NV = 1 << S;
+    constexpr int IT = NV >> 10;
+    constexpr int NW = NV >> 5;
+    constexpr int PER = NW / 64;
+    const int lane = this->lane;
+    LDS uint32_t* bw = this->beta + (o >> 5);
+    launder<S>();
+    if (this->tr) {
+#pragma unroll
+      for (int it = 0; it < IT; ++it)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            this->tr[o + 1024 * it + 16 * lane + 4 * k + b] = (int8_t)reg_elem<S>(it, k, b);
+    }
+    if (code == DOP_REP) {
+      // integers: every partial sum is exact, so the order is free
+      int sum = 0;
+#pragma unroll
+      for (int it = 0; it < IT; ++it)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) sum += reg_elem<S>(it, k, b);
+      float sf = (float)sum;
+      sf += __shfl_xor(sf, 32, 64);
+      sf += __shfl_xor(sf, 16, 64);
+      sf += __shfl_xor(sf, 8, 64);
+      sf += __shfl_xor(sf, 4, 64);
+      sf += __shfl_xor(sf, 2, 64);
+      sf += __shfl_xor(sf, 1, 64);
+      const bool bit = rflf(sf) < 0.0f;
+      for (int j = lane; j < NW; j += 64) bw[j] = bit ? ~0u : 0u;
+      this->pend_v = bit ? 1ull : 0ull;
+      this->pend_n = 1;
+      return;
+    }
+    // beta words to LDS: word 32 it + L/2 is the chunks of lanes L, L+1
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const uint32_t c = reg_hd16<S>(it);
+      const uint32_t up = from_up<1>(c);
+      if ((lane & 1) == 0) bw[32 * it + (lane >> 1)] = c | (up << 16);
+    }
+    wave_sync();
+    uint32_t wd[PER];
+    int par = 0;
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      wd[m] = bw[lane + 64 * m];
+      par ^= __popc(wd[m]);
+    }
+    if (code == DOP_SPC && (__popcll(ballot((par & 1) != 0)) & 1)) {
+      float best = 3.0e38f;
+      int bi = 0x7fffffff;
+#pragma unroll
+      for (int it = 0; it < IT; ++it)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int x = reg_elem<S>(it, k, b);
+            const float m = (float)(x < 0 ? -x : x);
+            if (m < best) {  // this lane's indices grow in this order
+              best = m;
+              bi = 1024 * it + 16 * lane + 4 * k + b;
+            }
+          }
+      const int idx = this->argmin_reduce(best, bi);
+      const int jw = idx >> 5;
+      if ((jw & 63) == lane) {
+#pragma unroll
+        for (int m = 0; m < PER; ++m)
+          if (m == (jw >> 6)) {
+            wd[m] ^= 1u << (idx & 31);
+            bw[jw] = wd[m];
+          }
+      }
+    }
+    this->template finish_leaf<S, PER>(wd, code, (LDS uint32_t*)this->stage(kTopLds));
+  }
+
+  // ----------------------------------------------------------- one op
+  template <uint32_t W>
+  __device__ __forceinline__ void step_c() {
+    constexpr uint32_t code = W & 0xffu;
+    constexpr int S = (int)((W >> 8) & 0xffu);
+    constexpr int o = (int)(W >> 16);
+    if constexpr (S <= kRegStages) {
+      if constexpr (code <= DOP_G0R)
+        this->template small_fg<S>(code, o);
+      else if constexpr (code <= DOP_CR0)
+        this->small_combine(code, S, o);
+      else if constexpr (code == DOP_FLUSH)
+        this->flush(o);
+      else
+        this->template small_leaf<S>(code, o);
+    } else if constexpr (code <= DOP_G0R) {
+      if constexpr (S == 7)
+        this->fg7(code);
+      else if constexpr (P::ELEM == 1)
+        fg_i8<S, code>(o);
+      else
+        fg_f32<S, code>(o);
+    } else if constexpr (code <= DOP_CR0) {
+      this->big_combine(code, S, o);
+    } else if constexpr (R::has(S)) {
+      leaf_reg<S>(code, o);
+    } else if constexpr (code == DOP_REP) {
+      this->big_leaf(code, S, o);
+    } else {
+      this->template leaf_r1spc<S>(code, o, S - 1 < kTopLds ? S - 1 : kTopLds);
+    }
+    if constexpr (code >= DOP_R1 && code <= DOP_SPC) this->settle();
+    wave_sync();
   }
 };
 

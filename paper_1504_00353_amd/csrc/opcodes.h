@@ -34,11 +34,13 @@ constexpr unsigned pack_op(unsigned code, int stage, int offset) {
 }
 
 // LDS bytes one wavefront needs: a 128-byte g sign table, the alpha stages
-// 7..log2n-1 (elem bytes per LLR) and the N-bit beta array, each 16-byte
-// aligned.
-constexpr int wave_lds_bytes(int log2n, int elem) {
-  return 128 + (((log2n > 7 ? ((1 << log2n) - 128) * elem : 0) + 15) & ~15) +
-         (((log2n > 6 ? (1 << log2n) / 8 : 0) + 15) & ~15);
+// 7..log2n-1-nreg (elem bytes per LLR; the top nreg stages may live in
+// registers instead) and the N-bit beta array, each 16-byte aligned.
+constexpr int alpha_lds_bytes(int log2n, int elem, int nreg) {
+  return log2n - nreg > 7 ? ((1 << (log2n - nreg)) - 128) * elem : 0;
+}
+constexpr int wave_lds_bytes(int log2n, int elem, int nreg = 0) {
+  return 128 + ((alpha_lds_bytes(log2n, elem, nreg) + 15) & ~15) + (((log2n > 6 ? (1 << log2n) / 8 : 0) + 15) & ~15);
 }
 
 }  // namespace polar

@@ -95,7 +95,15 @@ bool write_file_atomic(const std::string& path, const std::vector<char>& data) {
 
 }  // namespace
 
+int unrolled_nreg(int log2n, int llr_type) {
+  if (llr_type != 0) return 0;
+  if (log2n == 15) return 2;
+  if (log2n == 14) return 1;
+  return 0;
+}
+
 std::string unrolled_source(const Plan& p, int llr_type) {
+  const int nreg = unrolled_nreg(p.log2n, llr_type);
   const char* pol = llr_type == 1 ? "PF32" : "PI8";
   const char* chan = llr_type == 1 ? "float" : "int8_t";
   std::string s;
@@ -107,7 +115,7 @@ std::string unrolled_source(const Plan& p, int llr_type) {
   s += "template <class D>\n__device__ __forceinline__ void run(D& d) {\n";
   char line[80];
   for (int i = 0; i < p.nops; ++i) {
-    snprintf(line, sizeof line, "  d.template step_c<0x%08xu, %d>();\n", p.dops[i], p.log2n);
+    snprintf(line, sizeof line, "  d.template step_c<0x%08xu>();\n", p.dops[i]);
     s += line;
   }
   s += "}\n\n";
@@ -117,9 +125,10 @@ std::string unrolled_source(const Plan& p, int llr_type) {
   s += "  const int wid = (int)polar::rfl(threadIdx.x >> 6);\n";
   s += "  const int frame = blockIdx.x * (blockDim.x >> 6) + wid;\n";
   s += "  if (frame >= nframes) return;\n";
-  s += "  polar::Dec<polar::" + std::string(pol) + "> d;\n";
+  s += "  polar::DecU<polar::" + std::string(pol) + ", " + std::to_string(p.log2n) + ", " + std::to_string(nreg) +
+       "> d;\n";
   s += "  d.init((LDS unsigned char*)smem + wid * wave_bytes, lane, " + std::to_string(p.log2n) + ", " +
-       std::to_string(p.k) + ", llr, frame, bits, trace);\n";
+       std::to_string(p.k) + ", llr, frame, bits, trace, " + std::to_string(nreg) + ");\n";
   s += "  run(d);\n  d.finish();\n}\n\n}  // namespace\n\n";
   s += "extern \"C\" __global__ void __launch_bounds__(256) polar_unrolled(const " + std::string(chan) +
        "* __restrict__ llr, int nframes, uint8_t* __restrict__ bits, int wave_bytes) {\n";
@@ -201,7 +210,7 @@ void unrolled_unload(UnrolledKernel& k) {
 
 int unrolled_launch(const UnrolledKernel& k, int log2n, int llr_type, const void* llr, int nframes, uint8_t* bits,
                     void* trace, int waves_per_block, void* stream) {
-  int wb = wave_lds_bytes(log2n, llr_type == 1 ? 4 : 1);
+  int wb = wave_lds_bytes(log2n, llr_type == 1 ? 4 : 1, unrolled_nreg(log2n, llr_type));
   const unsigned grid = (unsigned)((nframes + waves_per_block - 1) / waves_per_block);
   const unsigned block = 64u * (unsigned)waves_per_block;
   const unsigned lds = (unsigned)wb * (unsigned)waves_per_block;

@@ -16,6 +16,10 @@ struct UnrolledKernel {
   hipFunction_t fn_trace = nullptr;
 };
 
+// Top alpha stages a generated kernel keeps in registers for this length
+// and LLR type (int8 codes of N >= 16384).
+int unrolled_nreg(int log2n, int llr_type);
+
 // HIP source of the two kernels (plain and tracing) for the plan's device
 // schedule and the LLR type (0 int8, 1 float).
 std::string unrolled_source(const Plan& p, int llr_type);

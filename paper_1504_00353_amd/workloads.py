@@ -62,4 +62,36 @@ UNROLLED_EXTRA = [
     (1024, 512, 2.5, "fastssc", "f32"),
     (256, 128, 2.5, "sc", "i8"),
     (4096, 3686, 4.0, "fastssc", "f32"),
+    (16384, 14746, 4.0, "fastssc", "i8"),
+    (32768, 16384, 2.5, "fastssc", "i8"),
 ]
+
+
+def _blocks(n, spec):
+    """Frozen mask from (kind, size) blocks laid end to end: kind "R0"
+    all frozen, "R1" none, "REP" all but the last, "SPC" only the first."""
+    mask = []
+    for kind, size in spec:
+        if kind == "R0":
+            mask += [1] * size
+        elif kind == "R1":
+            mask += [0] * size
+        elif kind == "REP":
+            mask += [1] * (size - 1) + [0]
+        else:
+            mask += [1] + [0] * (size - 1)
+    assert len(mask) == n
+    return mask
+
+
+# Frozen sets with every leaf kind at the widest node sizes of N = 32768 and
+# 16384 (the stages a generated int8 kernel keeps in registers).
+UNROLLED_MASKS = {
+    "m32k_spc13_rep13_spc14": (32768, _blocks(32768, [("SPC", 8192), ("REP", 8192), ("SPC", 16384)])),
+    "m32k_r013_r113_rep14": (32768, _blocks(32768, [("R0", 8192), ("R1", 8192), ("REP", 16384)])),
+    "m32k_r114_r014": (32768, _blocks(32768, [("R1", 16384), ("R0", 16384)])),
+    "m32k_rep12_spc12_r113_spc14": (32768, _blocks(32768, [("REP", 4096), ("SPC", 4096), ("R1", 8192),
+                                                           ("SPC", 16384)])),
+    "m16k_spc13_rep13": (16384, _blocks(16384, [("SPC", 8192), ("REP", 8192)])),
+    "m16k_r113_spc13": (16384, _blocks(16384, [("R1", 8192), ("SPC", 8192)])),
+}

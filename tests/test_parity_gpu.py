@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from frames import make_frames
-from paper_1504_00353_amd import Code, synth
+from paper_1504_00353_amd import Code, synth, workloads
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -191,7 +191,26 @@ def test_zero_frames_is_noop():
 
 def _unrolled_specs():
     from paper_1504_00353_amd import build
-    return build._kernel_specs()
+    return [t for t in build._kernel_specs() if t[1] != "mask"]
+
+
+@pytest.mark.parametrize("name", sorted(workloads.UNROLLED_MASKS))
+@pytest.mark.parametrize("kind", ["i8", "i8small"])
+def test_unrolled_kernel_masks(name, kind):
+    """Frozen sets with Rate-0, Rate-1, repetition and SPC nodes at the
+    widest stages (held in registers by the generated int8 kernels of
+    N >= 16384): bits and trace against the oracle, bits against the
+    schedule kernel."""
+    n, fr = workloads.UNROLLED_MASKS[name]
+    fr = np.asarray(fr, np.uint8)
+    code = Code(frozen=fr, kernel="unrolled")
+    ref = Code(frozen=fr, kernel="schedule")
+    rng = np.random.default_rng(n + len(name))
+    l = random_llrs(rng, 48, n, kind)
+    check_parity(code, fr, l, "fastssc", label="unrolled mask %s" % name)
+    b1, _ = gpu_decode(code, l)
+    b0, _ = gpu_decode(ref, l)
+    assert np.array_equal(b0, b1)
 
 
 @pytest.mark.parametrize("spec", _unrolled_specs(), ids=lambda t: "%d_%d_%s_%s" % (t[0], t[1], t[3], t[4]))
