@@ -163,6 +163,74 @@ polar_status polar_decode(const polar_code* code, const void* llr, int nframes, 
 polar_status polar_decode_trace(const polar_code* code, const void* llr, int nframes, uint8_t* bits,
                                 void* trace, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batches of mixed codes: one persistent launch decodes frames of several
+ * codes (lengths and rates) together.  Each code's decoder is its unrolled
+ * kernel (Sec. III-B) compiled into one generated kernel; every wavefront
+ * walks the frame list with a stride and decodes one frame at a time with
+ * the decoder of that frame's code, in an LDS slot sized for the largest
+ * code.  Results are identical to polar_decode on each code.
+ * ------------------------------------------------------------------------ */
+typedef struct polar_batch polar_batch; /* opaque; owned by the library */
+
+/* Builds a batch over ncodes (1..255) codes that share one LLR type (as
+ * configured; each code keeps its own algorithm).  The codes' schedules are
+ * copied; the codes may be destroyed afterwards.  Host only.
+ * Errors: POLAR_EINVAL (NULL, count, mixed LLR types), POLAR_ENOMEM. */
+polar_batch* polar_batch_create(const polar_code* const* codes, int ncodes);
+
+/* Compiles the batch kernel into the kernel cache unless it is there
+ * (host only; about a minute for fifteen codes up to N = 32768).
+ * Errors: POLAR_ECOMPILE, POLAR_ENOMEM. */
+polar_status polar_batch_build_kernel(const polar_batch* batch);
+
+/* Loads the batch kernel on the current device (building it first if the
+ * cache lacks it) and sets a default launch shape.  Synchronous.
+ * Errors: POLAR_EDEVICE, POLAR_ENOMEM, POLAR_ECOMPILE, POLAR_ESTATE. */
+polar_status polar_batch_prepare(polar_batch* batch);
+
+/* Describes the frames that polar_batch_decode() decodes: for frame i,
+ * code_index[i] (index into the codes given to polar_batch_create),
+ * llr_offset[i] (elements from the llr base pointer of the decode; the
+ * frame's N LLRs follow contiguously) and bits_offset[i] (bytes from the
+ * bits base pointer; the frame's ceil(K/8) output bytes follow).  Host
+ * arrays, copied.  The library orders frames longest code first and keeps
+ * the descriptors in device memory it owns (allocated here, grown when
+ * needed).  Synchronous.  Errors: POLAR_EINVAL (index or offset out of
+ * range), POLAR_ESTATE (not prepared), POLAR_ENOMEM, POLAR_EDEVICE. */
+polar_status polar_batch_set_frames(polar_batch* batch, int nframes, const int32_t* code_index,
+                                    const int64_t* llr_offset, const int64_t* bits_offset);
+
+/* Decodes the frames of the last polar_batch_set_frames() in one launch on
+ * the given stream.  Asynchronous; never allocates or synchronises, so it
+ * can be captured in a HIP graph (the descriptors must not change between
+ * capture and replay).  llr: device memory of the batch's LLR type, 4-byte
+ * aligned; bits: device memory.  Errors: POLAR_EINVAL, POLAR_ESTATE,
+ * POLAR_EDEVICE. */
+polar_status polar_batch_decode(const polar_batch* batch, const void* llr, uint8_t* bits, void* stream);
+
+/* As polar_batch_decode with caller-owned descriptors in device memory:
+ * desc[2i] = code index | bits byte offset << 8, desc[2i+1] = LLR offset in
+ * elements, for i < nframes (no ordering is applied; waves take frames i,
+ * i + W, i + 2W, ...).  The descriptors are not validated: indices and
+ * offsets must be in range. */
+polar_status polar_batch_decode_desc(const polar_batch* batch, const uint64_t* desc, int nframes,
+                                     const void* llr, uint8_t* bits, void* stream);
+
+/* Autotuner: times launch shapes (1, 2 or 4 frames per workgroup; a grid
+ * that fills the chip's wave slots once or twice, or one wave per frame)
+ * on the frames of the last polar_batch_set_frames() and keeps the
+ * fastest.  Runs decodes on the given buffers and synchronises.  Errors:
+ * POLAR_EINVAL, POLAR_ESTATE, POLAR_EDEVICE. */
+polar_status polar_batch_tune(polar_batch* batch, const void* llr, uint8_t* bits, void* stream);
+
+/* The current launch shape (any pointer may be NULL). */
+polar_status polar_batch_launch_shape(const polar_batch* batch, int* waves_per_block, int* blocks,
+                                      int* wave_lds_bytes);
+
+/* Frees the batch and its device memory.  NULL is a no-op. */
+void polar_batch_destroy(polar_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

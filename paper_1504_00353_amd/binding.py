@@ -20,7 +20,9 @@ EXPORTS = [
     "polar_construct", "polar_construct_mask", "polar_configure", "polar_prepare", "polar_destroy",
     "polar_last_status", "polar_strerror", "polar_n", "polar_k", "polar_frozen_mask", "polar_schedule",
     "polar_encode", "polar_decode", "polar_decode_trace", "polar_set_kernel", "polar_build_kernel",
-    "polar_last_message",
+    "polar_last_message", "polar_batch_create", "polar_batch_build_kernel", "polar_batch_prepare",
+    "polar_batch_set_frames", "polar_batch_decode", "polar_batch_decode_desc", "polar_batch_tune",
+    "polar_batch_launch_shape", "polar_batch_destroy",
 ]
 
 
@@ -65,6 +67,17 @@ def _lib():
         L.polar_encode.argtypes = [P, P, I, P]
         L.polar_decode.argtypes = [P, P, I, P, P]
         L.polar_decode_trace.argtypes = [P, P, I, P, P, P]
+        L.polar_batch_create.argtypes = [P, I]
+        L.polar_batch_create.restype = P
+        L.polar_batch_build_kernel.argtypes = [P]
+        L.polar_batch_prepare.argtypes = [P]
+        L.polar_batch_set_frames.argtypes = [P, I, P, P, P]
+        L.polar_batch_decode.argtypes = [P, P, P, P]
+        L.polar_batch_decode_desc.argtypes = [P, P, I, P, P, P]
+        L.polar_batch_tune.argtypes = [P, P, P, P]
+        L.polar_batch_launch_shape.argtypes = [P, P, P, P]
+        L.polar_batch_destroy.argtypes = [P]
+        L.polar_batch_destroy.restype = None
         _L = L
     return _L
 
@@ -191,3 +204,72 @@ class Code:
                                          ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(trace.data_ptr()),
                                          _stream_handle(stream)), "polar_decode_trace")
         return out, trace
+
+
+class Batch:
+    """Frames of several codes (one LLR type) decoded in one persistent
+    launch; see polar_batch_* in include/polar.h."""
+
+    def __init__(self, codes, prepare=True):
+        L = _lib()
+        self.codes = list(codes)
+        arr = (ctypes.c_void_p * len(self.codes))(*[c.handle.value for c in self.codes])
+        h = L.polar_batch_create(arr, len(self.codes))
+        if not h:
+            raise PolarError(L.polar_last_status(), "polar_batch_create")
+        self._h = ctypes.c_void_p(h)
+        self.llr = self.codes[0].llr
+        self.nframes = 0
+        if prepare:
+            self.prepare()
+
+    def build_kernel(self):
+        _check(_lib().polar_batch_build_kernel(self._h), "polar_batch_build_kernel")
+
+    def prepare(self):
+        _check(_lib().polar_batch_prepare(self._h), "polar_batch_prepare")
+
+    def set_frames(self, code_index, llr_offset, bits_offset):
+        ci = np.ascontiguousarray(code_index, dtype=np.int32)
+        lo = np.ascontiguousarray(llr_offset, dtype=np.int64)
+        bo = np.ascontiguousarray(bits_offset, dtype=np.int64)
+        if not (ci.shape == lo.shape == bo.shape) or ci.ndim != 1:
+            raise ValueError("code_index, llr_offset and bits_offset must be 1-D of one length")
+        _check(_lib().polar_batch_set_frames(self._h, ci.shape[0], _np_ptr(ci), _np_ptr(lo), _np_ptr(bo)),
+               "polar_batch_set_frames")
+        self.nframes = int(ci.shape[0])
+
+    def decode(self, llr, bits, stream=None):
+        """Decode the described frames: llr and bits are flat CUDA tensors
+        (LLR dtype / uint8) that the descriptors' offsets index."""
+        _check(_lib().polar_batch_decode(self._h, ctypes.c_void_p(llr.data_ptr()), ctypes.c_void_p(bits.data_ptr()),
+                                         _stream_handle(stream)), "polar_batch_decode")
+        return bits
+
+    def decode_desc(self, desc, nframes, llr, bits, stream=None):
+        _check(_lib().polar_batch_decode_desc(self._h, ctypes.c_void_p(desc.data_ptr()), int(nframes),
+                                              ctypes.c_void_p(llr.data_ptr()), ctypes.c_void_p(bits.data_ptr()),
+                                              _stream_handle(stream)), "polar_batch_decode_desc")
+        return bits
+
+    def tune(self, llr, bits, stream=None):
+        _check(_lib().polar_batch_tune(self._h, ctypes.c_void_p(llr.data_ptr()), ctypes.c_void_p(bits.data_ptr()),
+                                       _stream_handle(stream)), "polar_batch_tune")
+        return self.launch_shape()
+
+    def launch_shape(self):
+        w, b, l = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        _check(_lib().polar_batch_launch_shape(self._h, ctypes.byref(w), ctypes.byref(b), ctypes.byref(l)),
+               "polar_batch_launch_shape")
+        return {"waves_per_block": w.value, "blocks": b.value, "wave_lds_bytes": l.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().polar_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

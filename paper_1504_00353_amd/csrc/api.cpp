@@ -2,9 +2,10 @@
 // device upload and the host encoder.  See include/polar.h.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cstring>
-#include <string>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/polar.h"
@@ -27,6 +28,23 @@ struct polar_code {
   int nops = 0;
   int waves_per_block = 1;
   polar::UnrolledKernel unrolled;
+};
+
+struct polar_batch {
+  std::vector<polar::Plan> plans;  // copies of the codes' schedules
+  int llr_type = POLAR_LLR_I8;
+  int wave_bytes = 0;              // LDS slot of one wave: the largest code's need
+  int waves_per_simd = 1;          // occupancy the generated kernel's registers are held to
+  bool prepared = false;
+  int device = -1;
+  int cus = 0;
+  hipModule_t module = nullptr;
+  hipFunction_t fn = nullptr;
+  int waves_per_block = 4;
+  int blocks = 0;
+  unsigned long long* d_desc = nullptr;  // descriptors from polar_batch_set_frames
+  int desc_cap = 0;
+  int nframes = 0;
 };
 
 namespace {
@@ -294,6 +312,228 @@ polar_status polar_decode_trace(const polar_code* c, const void* llr, int nframe
                                 void* stream) {
   if (nframes > 0 && !trace) return set(POLAR_EINVAL);
   return decode_impl(c, llr, nframes, bits, trace, stream);
+}
+
+
+/* ------------------------------------------------------------------ batch */
+
+namespace {
+
+int batch_occupancy(int wave_bytes, int lds_per_cu) {
+  // waves of one SIMD (4 per CU) that the LDS allows, 1..4
+  int per_cu = wave_bytes > 0 ? lds_per_cu / wave_bytes : 32;
+  int w = per_cu / 4;
+  return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
+std::string batch_src(const polar_batch* b) {
+  std::vector<const polar::Plan*> ps;
+  for (const auto& p : b->plans) ps.push_back(&p);
+  return polar::batch_source(ps, b->llr_type, b->waves_per_simd);
+}
+
+}  // namespace
+
+polar_batch* polar_batch_create(const polar_code* const* codes, int ncodes) {
+  if (!codes || ncodes < 1 || ncodes > 255) {
+    set(POLAR_EINVAL);
+    return nullptr;
+  }
+  for (int i = 0; i < ncodes; ++i)
+    if (!codes[i] || codes[i]->llr_type != codes[0]->llr_type) {
+      set(POLAR_EINVAL);
+      return nullptr;
+    }
+  polar_batch* b = new (std::nothrow) polar_batch;
+  if (!b) {
+    set(POLAR_ENOMEM);
+    return nullptr;
+  }
+  try {
+    b->llr_type = codes[0]->llr_type;
+    const int elem = b->llr_type == POLAR_LLR_F32 ? 4 : 1;
+    for (int i = 0; i < ncodes; ++i) {
+      b->plans.push_back(codes[i]->plan);
+      const int l2 = codes[i]->plan.log2n;
+      b->wave_bytes = std::max(b->wave_bytes, polar::wave_lds_bytes(l2, elem, polar::unrolled_nreg(l2, b->llr_type)));
+    }
+  } catch (const std::bad_alloc&) {
+    delete b;
+    set(POLAR_ENOMEM);
+    return nullptr;
+  }
+  b->waves_per_simd = batch_occupancy(b->wave_bytes, 160 * 1024);
+  set(POLAR_OK);
+  return b;
+}
+
+polar_status polar_batch_build_kernel(const polar_batch* b) {
+  if (!b) return set(POLAR_EINVAL);
+  try {
+    std::vector<char> code;
+    std::string log;
+    if (polar::source_code_object(batch_src(b), code, log) != 0) return set_msg(POLAR_ECOMPILE, log);
+  } catch (const std::bad_alloc&) {
+    return set(POLAR_ENOMEM);
+  }
+  return set(POLAR_OK);
+}
+
+polar_status polar_batch_prepare(polar_batch* b) {
+  if (!b) return set(POLAR_EINVAL);
+  if (b->prepared) return set(POLAR_ESTATE);
+  int dev = 0, cus = 0, lds_max = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return set(POLAR_EDEVICE);
+  if (b->wave_bytes > lds_max) return set(POLAR_ENOMEM);
+  try {
+    std::vector<char> code;
+    std::string log;
+    if (polar::source_code_object(batch_src(b), code, log) != 0) return set_msg(POLAR_ECOMPILE, log);
+    if (polar::batch_load(code, b->module, b->fn) != 0) return set(POLAR_EDEVICE);
+  } catch (const std::bad_alloc&) {
+    return set(POLAR_ENOMEM);
+  }
+  b->device = dev;
+  b->cus = cus;
+  int wpb = lds_max / b->wave_bytes;
+  b->waves_per_block = wpb < 1 ? 1 : (wpb > 4 ? 4 : wpb);
+  // enough workgroups for every wave slot of the chip, each looping over frames
+  b->blocks = cus * ((4 * b->waves_per_simd) / b->waves_per_block);
+  if (b->blocks < 1) b->blocks = 1;
+  b->prepared = true;
+  return set(POLAR_OK);
+}
+
+polar_status polar_batch_set_frames(polar_batch* b, int nframes, const int32_t* code_index, const int64_t* llr_offset,
+                                    const int64_t* bits_offset) {
+  if (!b || nframes < 0 || (nframes > 0 && (!code_index || !llr_offset || !bits_offset))) return set(POLAR_EINVAL);
+  if (!b->prepared) return set(POLAR_ESTATE);
+  const int ncodes = (int)b->plans.size();
+  std::vector<unsigned long long> desc;
+  try {
+    std::vector<int> order(nframes);
+    for (int i = 0; i < nframes; ++i) {
+      if (code_index[i] < 0 || code_index[i] >= ncodes || llr_offset[i] < 0 || bits_offset[i] < 0 ||
+          bits_offset[i] >= (1ll << 56))
+        return set(POLAR_EINVAL);
+      order[i] = i;
+    }
+    // longest codes first, so the waves' strided walks finish together
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return b->plans[code_index[x]].n > b->plans[code_index[y]].n;
+    });
+    desc.resize(2 * (size_t)nframes);
+    for (int j = 0; j < nframes; ++j) {
+      const int i = order[j];
+      desc[2 * j] = (unsigned long long)code_index[i] | ((unsigned long long)bits_offset[i] << 8);
+      desc[2 * j + 1] = (unsigned long long)llr_offset[i];
+    }
+  } catch (const std::bad_alloc&) {
+    return set(POLAR_ENOMEM);
+  }
+  if (nframes > b->desc_cap) {
+    unsigned long long* d = nullptr;
+    if (hipMalloc((void**)&d, desc.size() * sizeof(unsigned long long)) != hipSuccess) return set(POLAR_ENOMEM);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    b->d_desc = d;
+    b->desc_cap = nframes;
+  }
+  if (nframes > 0 &&
+      hipMemcpy(b->d_desc, desc.data(), desc.size() * sizeof(unsigned long long), hipMemcpyHostToDevice) != hipSuccess)
+    return set(POLAR_EDEVICE);
+  b->nframes = nframes;
+  return set(POLAR_OK);
+}
+
+polar_status polar_batch_decode_desc(const polar_batch* b, const uint64_t* desc, int nframes, const void* llr,
+                                     uint8_t* bits, void* stream) {
+  if (!b || nframes < 0) return set(POLAR_EINVAL);
+  if (!b->prepared) return set(POLAR_ESTATE);
+  if (nframes == 0) return set(POLAR_OK);
+  if (!desc || !llr || !bits || ((uintptr_t)llr & 3u) != 0) return set(POLAR_EINVAL);
+  const int rc = polar::batch_launch(b->fn, desc, nframes, llr, bits, b->wave_bytes, b->waves_per_block, b->blocks,
+                                     stream);
+  return set(rc == 0 ? POLAR_OK : POLAR_EDEVICE);
+}
+
+polar_status polar_batch_decode(const polar_batch* b, const void* llr, uint8_t* bits, void* stream) {
+  if (!b) return set(POLAR_EINVAL);
+  return polar_batch_decode_desc(b, (const uint64_t*)b->d_desc, b->nframes, llr, bits, stream);
+}
+
+polar_status polar_batch_tune(polar_batch* b, const void* llr, uint8_t* bits, void* stream) {
+  if (!b) return set(POLAR_EINVAL);
+  if (!b->prepared) return set(POLAR_ESTATE);
+  if (b->nframes == 0) return set(POLAR_OK);
+  if (!llr || !bits) return set(POLAR_EINVAL);
+  int lds_max = 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) != hipSuccess)
+    return set(POLAR_EDEVICE);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return set(POLAR_EDEVICE);
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return set(POLAR_EDEVICE);
+  }
+  const int slots = b->cus * 4 * b->waves_per_simd;  // resident waves on the chip
+  int best_wpb = b->waves_per_block, best_blocks = b->blocks;
+  float best = -1.0f;
+  polar_status st = POLAR_OK;
+  for (int wpb = 1; wpb <= 4 && st == POLAR_OK; wpb <<= 1) {
+    if (wpb * b->wave_bytes > lds_max) break;
+    // resident grid, twice resident (late waves fill the tail), one wave per frame
+    const int cands[3] = {slots / wpb, 2 * slots / wpb, (b->nframes + wpb - 1) / wpb};
+    for (int c = 0; c < 3 && st == POLAR_OK; ++c) {
+      const int blocks = cands[c] < 1 ? 1 : cands[c];
+      float ms_best = -1.0f;
+      for (int rep = 0; rep < 4; ++rep) {  // first launch warms up
+        if (hipEventRecord(e0, (hipStream_t)stream) != hipSuccess ||
+            polar::batch_launch(b->fn, b->d_desc, b->nframes, llr, bits, b->wave_bytes, wpb, blocks, stream) != 0 ||
+            hipEventRecord(e1, (hipStream_t)stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          st = POLAR_EDEVICE;
+          break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0 && (ms_best < 0.0f || ms < ms_best)) ms_best = ms;
+      }
+      if (st == POLAR_OK && (best < 0.0f || ms_best < best)) {
+        best = ms_best;
+        best_wpb = wpb;
+        best_blocks = blocks;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != POLAR_OK) return set(st);
+  b->waves_per_block = best_wpb;
+  b->blocks = best_blocks;
+  return set(POLAR_OK);
+}
+
+polar_status polar_batch_launch_shape(const polar_batch* b, int* waves_per_block, int* blocks, int* wave_lds_bytes) {
+  if (!b) return set(POLAR_EINVAL);
+  if (waves_per_block) *waves_per_block = b->waves_per_block;
+  if (blocks) *blocks = b->blocks;
+  if (wave_lds_bytes) *wave_lds_bytes = b->wave_bytes;
+  return set(POLAR_OK);
+}
+
+void polar_batch_destroy(polar_batch* b) {
+  if (!b) return;
+  if (b->module || b->d_desc) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != b->device) (void)hipSetDevice(b->device);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->module) (void)hipModuleUnload(b->module);
+    if (cur != b->device) (void)hipSetDevice(cur);
+  }
+  delete b;
 }
 
 }  // extern "C"

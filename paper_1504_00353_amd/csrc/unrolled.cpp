@@ -142,6 +142,54 @@ std::string unrolled_source(const Plan& p, int llr_type) {
   return s;
 }
 
+std::string batch_source(const std::vector<const Plan*>& plans, int llr_type, int waves_per_simd) {
+  const char* pol = llr_type == 1 ? "PF32" : "PI8";
+  const char* chan = llr_type == 1 ? "float" : "int8_t";
+  std::string s;
+  size_t total_ops = 0;
+  for (const Plan* p : plans) total_ops += (size_t)p->nops;
+  s.reserve(64 * total_ops + 4096 * plans.size() + 4096);
+  s += "// generated: persistent batch decoder for " + std::to_string(plans.size()) + " polar codes\n";
+  s += "#include \"decode_ops.h\"\n\nnamespace {\n\n";
+  char line[96];
+  for (size_t c = 0; c < plans.size(); ++c) {
+    const Plan& p = *plans[c];
+    const int nreg = unrolled_nreg(p.log2n, llr_type);
+    s += "// code " + std::to_string(c) + ": N=" + std::to_string(p.n) + " K=" + std::to_string(p.k) +
+         " algo=" + std::to_string(p.algo) + "\n";
+    s += "__device__ __noinline__ void dec_" + std::to_string(c) + "(LDS unsigned char* base, int lane, const " +
+         chan + "* llr, uint8_t* bits) {\n";
+    s += "  polar::DecU<polar::" + std::string(pol) + ", " + std::to_string(p.log2n) + ", " + std::to_string(nreg) +
+         "> d;\n";
+    s += "  d.init(base, lane, " + std::to_string(p.log2n) + ", " + std::to_string(p.k) + ", llr, 0, bits, nullptr, " +
+         std::to_string(nreg) + ");\n";
+    for (int i = 0; i < p.nops; ++i) {
+      snprintf(line, sizeof line, "  d.template step_c<0x%08xu>();\n", p.dops[i]);
+      s += line;
+    }
+    s += "  d.finish();\n}\n\n";
+  }
+  s += "}  // namespace\n\n";
+  // Frame descriptor: two 64-bit words, [0] = code index | bits byte offset << 8,
+  // [1] = LLR offset in elements.  Each wave takes frames wave, wave + W, ...
+  s += "extern \"C\" __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(" +
+       std::to_string(waves_per_simd) + "))) polar_batch(const unsigned long long* __restrict__ desc, int nframes, const " +
+       chan + "* __restrict__ llr, uint8_t* __restrict__ bits, int wave_bytes) {\n";
+  s += "  extern __shared__ __align__(16) unsigned char smem[];\n";
+  s += "  const int lane = threadIdx.x & 63;\n";
+  s += "  const int wid = (int)polar::rfl(threadIdx.x >> 6);\n";
+  s += "  LDS unsigned char* base = (LDS unsigned char*)smem + wid * wave_bytes;\n";
+  s += "  const int stride = gridDim.x * (blockDim.x >> 6);\n";
+  s += "  for (int f = blockIdx.x * (blockDim.x >> 6) + wid; f < nframes; f += stride) {\n";
+  s += "    const unsigned long long d0 = desc[2 * f], d1 = desc[2 * f + 1];\n";
+  s += "    switch ((unsigned)(d0 & 255u)) {\n";
+  for (size_t c = 0; c < plans.size(); ++c)
+    s += "      case " + std::to_string(c) + ": dec_" + std::to_string(c) +
+         "(base, lane, llr + d1, bits + (d0 >> 8)); break;\n";
+  s += "      default: break;\n    }\n  }\n}\n";
+  return s;
+}
+
 std::string unrolled_cache_path(const std::string& src) {
   uint64_t h = 0xcbf29ce484222325ull;
   h = fnv1a(h, src.data(), src.size());
@@ -160,7 +208,10 @@ std::string unrolled_cache_path(const std::string& src) {
 // Returns 0 and the code object, from the cache or freshly compiled (and
 // then stored), or -1 with the compiler log.
 int unrolled_code_object(const Plan& p, int llr_type, std::vector<char>& code, std::string& log) {
-  const std::string src = unrolled_source(p, llr_type);
+  return source_code_object(unrolled_source(p, llr_type), code, log);
+}
+
+int source_code_object(const std::string& src, std::vector<char>& code, std::string& log) {
   const std::string path = unrolled_cache_path(src);
   if (read_file(path, code)) return 0;
   hiprtcProgram prog;
@@ -190,6 +241,24 @@ int unrolled_code_object(const Plan& p, int llr_type, std::vector<char>& code, s
   mkdir(dir.c_str(), 0755);  // may exist; a failed store only costs a recompile later
   (void)write_file_atomic(path, code);
   return 0;
+}
+
+int batch_load(const std::vector<char>& code, hipModule_t& module, hipFunction_t& fn) {
+  if (hipModuleLoadData(&module, code.data()) != hipSuccess) return -1;
+  if (hipModuleGetFunction(&fn, module, "polar_batch") != hipSuccess) {
+    (void)hipModuleUnload(module);
+    module = nullptr;
+    return -1;
+  }
+  return 0;
+}
+
+int batch_launch(hipFunction_t fn, const void* desc, int nframes, const void* llr, uint8_t* bits, int wave_bytes,
+                 int waves_per_block, int blocks, void* stream) {
+  const unsigned lds = (unsigned)wave_bytes * (unsigned)waves_per_block;
+  void* args[] = {(void*)&desc, (void*)&nframes, (void*)&llr, (void*)&bits, (void*)&wave_bytes};
+  return (int)hipModuleLaunchKernel(fn, (unsigned)blocks, 1, 1, 64u * (unsigned)waves_per_block, 1, 1, lds,
+                                    (hipStream_t)stream, args, nullptr);
 }
 
 int unrolled_load(const std::vector<char>& code, UnrolledKernel& k) {

@@ -28,6 +28,16 @@ std::string unrolled_source(const Plan& p, int llr_type);
 // stored.  0 on success; -1 with the compiler log otherwise.
 int unrolled_code_object(const Plan& p, int llr_type, std::vector<char>& code, std::string& log);
 
+// Code object for any generated source (cache, else compile and store).
+int source_code_object(const std::string& src, std::vector<char>& code, std::string& log);
+
+// HIP source of the persistent batch kernel over several codes of one LLR
+// type; waves_per_simd: the occupancy its register use is held to.
+std::string batch_source(const std::vector<const Plan*>& plans, int llr_type, int waves_per_simd);
+int batch_load(const std::vector<char>& code, hipModule_t& module, hipFunction_t& fn);
+int batch_launch(hipFunction_t fn, const void* desc, int nframes, const void* llr, uint8_t* bits, int wave_bytes,
+                 int waves_per_block, int blocks, void* stream);
+
 // Loads a code object on the current device.  0 on success.
 int unrolled_load(const std::vector<char>& code, UnrolledKernel& k);
 void unrolled_unload(UnrolledKernel& k);

@@ -145,3 +145,25 @@ def test_unrolled_kernel_builds_with_torch_loaded(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0 and "built" in r.stdout, r.stdout + r.stderr
     assert len(os.listdir(tmp_path)) == 3
+
+
+def test_batch_arguments_and_build(tmp_path, monkeypatch):
+    """Batch creation checks its codes; set_frames before prepare is out of
+    order; the batch kernel of two small codes builds on the host."""
+    L = binding.lib()
+    monkeypatch.setenv("POLAR_KERNEL_CACHE", str(tmp_path))
+    assert not L.polar_batch_create(None, 1)
+    assert L.polar_last_status() == binding.EINVAL
+    a = binding.Code(64, 32, 2.5, prepare=False)
+    b = binding.Code(128, 100, 4.0, llr="f32", prepare=False)
+    arr = (ctypes.c_void_p * 2)(a.handle.value, b.handle.value)
+    assert not L.polar_batch_create(arr, 2)  # mixed LLR types
+    assert L.polar_last_status() == binding.EINVAL
+    c = binding.Code(128, 100, 4.0, prepare=False)
+    bt = binding.Batch([a, c], prepare=False)
+    with pytest.raises(binding.PolarError):
+        bt.set_frames([0], [0], [0])  # not prepared
+    bt.build_kernel()
+    assert len(os.listdir(tmp_path)) == 1
+    assert L.polar_batch_decode(None, None, None, None) == binding.EINVAL
+    L.polar_batch_destroy(None)
