@@ -10,7 +10,9 @@ Gb/s single-core figure for this code.  Prints one JSON line:
   plain        the same frames decoded with one launch per frame;
   roofline     algorithmic HBM bytes (LLR in + info bits out) per launch
                over the decode kernel's mean duration vs 8 TB/s;
-  cpu_baseline the CPU oracle on a bounded sample on this host's cores.
+  cpu_baseline the CPU oracle on a bounded sample on this host's cores;
+  mixed_batch  the 65,536-frame mixed-code workload in one persistent,
+               autotuned launch (information Gb/s, launch time, FER).
 """
 import argparse
 import hashlib
@@ -92,6 +94,67 @@ def copy_calibration(nbytes, reps):
                       "kernel": "elementwise bitwise_not int8 (reads and writes each byte once)"}), flush=True)
 
 
+def mixed_batch_bench(steps, pool_frames=4096, frames=65536, seed=3):
+    """The mixed workload in one persistent launch: 65,536 frames, code
+    uniform over N in {256, ..., 32768} x R in {0.5, 0.83, 0.9}, Eb/N0
+    uniform 2-5 dB per frame, int8.  The LLRs of pool_frames distinct frames
+    are generated; the 65,536 descriptors pick among them."""
+    import torch
+    from paper_1504_00353_amd import Batch, Code, synth, workloads as W
+    codes = [Code(n, k, d, llr="i8", prepare=False) for n, k, d in W.MIXED["codes"]]
+    batch = Batch(codes)
+    idx = np.arange(pool_frames)
+    cidx, ebn0 = synth.frame_params(seed, idx, [list(range(len(codes))), W.MIXED["ebn0_db"]])
+    cidx = np.asarray(cidx, np.int32)
+    ebn0 = np.asarray(ebn0)
+    sizes = np.array([codes[c].n for c in cidx], np.int64)
+    poffs = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    flat = np.zeros(int(sizes.sum()), np.int8)
+    infos = [None] * pool_frames
+    for c, code in enumerate(codes):
+        sel = np.flatnonzero(cidx == c)
+        if sel.size == 0:
+            continue
+        bits = synth.info_bits(seed, sel, code.k)
+        x = synth.unpack_bits(code.encode(synth.pack_bits(bits)), code.n)
+        l = synth.quantize6(synth.awgn_llr(x, synth.noise(seed, sel, code.n), ebn0[sel], code.k / code.n))
+        for j, f in enumerate(sel):
+            flat[poffs[f]:poffs[f] + code.n] = l[j]
+            infos[f] = bits[j]
+    pick = np.random.default_rng(seed).integers(0, pool_frames, size=frames)
+    code_idx = cidx[pick]
+    rb = np.array([codes[c].row_bytes for c in code_idx], np.int64)
+    bo = np.concatenate([[0], np.cumsum(rb)[:-1]]).astype(np.int64)
+    batch.set_frames(code_idx, poffs[pick], bo)
+    llr = torch.from_numpy(flat).cuda()
+    out = torch.zeros(int(rb.sum()), dtype=torch.uint8, device="cuda")
+    shape = batch.tune(llr, out)
+    stream = torch.cuda.current_stream()
+    batch.decode(llr, out)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        batch.decode(llr, out)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = [a.elapsed_time(b) for a, b in ev]
+    info_bits = float(sum(codes[c].k for c in code_idx))
+    o = out.cpu().numpy()
+    fe = 0
+    for i in range(frames):
+        f = pick[i]
+        got = synth.unpack_bits(o[bo[i]:bo[i] + rb[i]][None], codes[code_idx[i]].k)[0]
+        fe += int((got != infos[f]).any())
+    return {"frames": frames, "distinct_frames": pool_frames, "codes": len(codes),
+            "value": round(info_bits * steps / wall / 1e9, 3), "unit": "Gbps",
+            "mean_kernel_ms": round(float(np.mean(ms)), 4),
+            "launch_ms": {"p50": round(percentile(ms, 50), 4), "p99": round(percentile(ms, 99), 4)},
+            "fer": round(fe / frames, 5), "launch_shape": shape}
+
+
 def percentile(v, p):
     return float(np.percentile(np.asarray(v, np.float64), p))
 
@@ -125,6 +188,7 @@ def main():
     ap.add_argument("--latency-runs", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-code batch measurement")
     ap.add_argument("--kernel", choices=["unrolled", "schedule"], default="unrolled",
                     help="generated per-code kernel (default) or the schedule-interpreting one")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -244,6 +308,8 @@ def main():
                      "bytes_per_frame": bytes_per_frame,
                      "mean_kernel_ms": round(mean_kernel_s * 1e3, 4)},
     }
+    if not args.no_mixed and args.kernel == "unrolled":
+        result["mixed_batch"] = mixed_batch_bench(max(args.steps // 2, 3))
     if not args.no_cpu:
         done, dt, threads, one_core_us = cpu_baseline(frozen, llr_np, args.cpu_seconds)
         result["cpu_baseline"] = {"value": round(done * k / dt / 1e9, 5), "unit": "Gbps", "cores": threads,

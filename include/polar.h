@@ -25,6 +25,7 @@
 #ifndef POLAR_H
 #define POLAR_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -41,7 +42,8 @@ typedef enum {
   POLAR_EDEVICE = 3, /* a HIP call failed (launch error, no device) */
   POLAR_ESTATE = 4,  /* call out of order: e.g. decode before prepare,
                         configure after prepare */
-  POLAR_ECOMPILE = 5 /* the code's unrolled kernel failed to compile */
+  POLAR_ECOMPILE = 5, /* the code's unrolled kernel failed to compile */
+  POLAR_EAGAIN = 6    /* no room right now (request server): poll, then retry */
 } polar_status;
 
 typedef enum { POLAR_ALGO_FASTSSC = 0, POLAR_ALGO_SC = 1 } polar_algo;
@@ -230,6 +232,60 @@ polar_status polar_batch_launch_shape(const polar_batch* batch, int* waves_per_b
 
 /* Frees the batch and its device memory.  NULL is a no-op. */
 void polar_batch_destroy(polar_batch* batch);
+
+/* ------------------------------------------------------------------------
+ * Request server: continuous batching of decode requests over a prepared
+ * batch.  A request is 1..n frames of one of the batch's codes, LLRs and
+ * results in host memory.  Requests are admitted first come, first served
+ * as soon as device slots for all their frames are free; every poll
+ * retires finished steps, admits what fits and launches one step (one
+ * persistent batch decode) over all admitted frames not yet launched, on a
+ * free server stream, so successive steps overlap on the device and
+ * requests that arrive while a step runs join the next.  Each frame is
+ * decoded exactly as polar_decode would decode it alone.
+ * Not thread safe: one thread drives a server.
+ * ------------------------------------------------------------------------ */
+typedef struct polar_server polar_server; /* opaque; owned by the library */
+
+/* Creates a server on the current device for a prepared batch; codes /
+ * ncodes must be the codes the batch was created from, in the same order.
+ * slots_per_class: device frame slots for each distinct frame length N
+ * (device memory: slots x (N x LLR size + ceil(K/8)) per length);
+ * streams: steps in flight at once (1..8); staging_bytes: pinned host
+ * memory holding submitted LLRs until their step has copied them.
+ * Allocates device and pinned host memory.  NULL on error (see
+ * polar_last_status: POLAR_EINVAL, POLAR_ESTATE if the batch is not
+ * prepared, POLAR_ENOMEM, POLAR_EDEVICE). */
+polar_server* polar_server_create(const polar_batch* batch, const polar_code* const* codes, int ncodes,
+                                  int slots_per_class, int streams, size_t staging_bytes);
+
+/* Queues a request of nframes frames of code code_index (an index into
+ * the batch's codes).  llr: [nframes][N] LLRs of the batch's type, either
+ * host memory (llr_on_device = 0: copied to pinned staging before the call
+ * returns, then to a device slot by the request's step) or device memory
+ * on the server's device (llr_on_device = 1: read in place, no copy; it
+ * must stay valid until the request is reported done).  bits: host memory
+ * [nframes][ceil(K/8)], written by the poll that reports the request done;
+ * it must stay valid until then.  *id receives the request id (> 0).
+ * Errors: POLAR_EINVAL (bad arguments, or more frames than the code's
+ * length class has slots), POLAR_EAGAIN (staging memory full: poll, then
+ * submit again). */
+polar_status polar_server_submit(polar_server* server, int code_index, int nframes, const void* llr,
+                                 int llr_on_device, uint8_t* bits, int64_t* id);
+
+/* Makes progress without blocking: retires finished steps (writing their
+ * requests' bits), admits waiting requests, launches a step.  Writes the
+ * ids of requests completed by this call to done_ids (at most cap; *ndone
+ * receives the count).  Errors: POLAR_EINVAL, POLAR_EDEVICE. */
+polar_status polar_server_poll(polar_server* server, int64_t* done_ids, int cap, int* ndone);
+
+/* Requests waiting for slots, admitted but not launched, and steps in
+ * flight (any pointer may be NULL). */
+polar_status polar_server_pending(const polar_server* server, int* waiting, int* admitted, int* inflight_steps);
+
+/* Waits for the server's streams, then frees it.  Requests not yet
+ * reported by a poll are dropped.  NULL is a no-op. */
+void polar_server_destroy(polar_server* server);
 
 #ifdef __cplusplus
 }

@@ -4,4 +4,4 @@ The decoder is the one of Giard et al., "Low-Latency Software Polar
 Decoders", re-designed for CDNA4 wavefronts; see include/polar.h for the C
 ABI.  This package is a thin ctypes binding over libpolar.so.
 """
-from .binding import Batch, Code, PolarError, lib  # noqa: F401
+from .binding import Batch, Code, PolarError, Server, lib  # noqa: F401

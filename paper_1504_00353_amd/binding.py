@@ -11,7 +11,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.path.join(_HERE, "libpolar.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ECOMPILE = 0, 1, 2, 3, 4, 5
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ECOMPILE, EAGAIN = 0, 1, 2, 3, 4, 5, 6
 ALGO = {"fastssc": 0, "sc": 1}
 LLR = {"i8": 0, "f32": 1}
 KERNEL = {"schedule": 0, "unrolled": 1}
@@ -22,7 +22,8 @@ EXPORTS = [
     "polar_encode", "polar_decode", "polar_decode_trace", "polar_set_kernel", "polar_build_kernel",
     "polar_last_message", "polar_batch_create", "polar_batch_build_kernel", "polar_batch_prepare",
     "polar_batch_set_frames", "polar_batch_decode", "polar_batch_decode_desc", "polar_batch_tune",
-    "polar_batch_launch_shape", "polar_batch_destroy",
+    "polar_batch_launch_shape", "polar_batch_destroy", "polar_server_create", "polar_server_submit",
+    "polar_server_poll", "polar_server_pending", "polar_server_destroy",
 ]
 
 
@@ -78,6 +79,13 @@ def _lib():
         L.polar_batch_launch_shape.argtypes = [P, P, P, P]
         L.polar_batch_destroy.argtypes = [P]
         L.polar_batch_destroy.restype = None
+        L.polar_server_create.argtypes = [P, P, I, I, I, ctypes.c_size_t]
+        L.polar_server_create.restype = P
+        L.polar_server_submit.argtypes = [P, I, I, P, I, P, P]
+        L.polar_server_poll.argtypes = [P, P, I, P]
+        L.polar_server_pending.argtypes = [P, P, P, P]
+        L.polar_server_destroy.argtypes = [P]
+        L.polar_server_destroy.restype = None
         _L = L
     return _L
 
@@ -266,6 +274,77 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             _lib().polar_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server over a prepared Batch; see
+    polar_server_* in include/polar.h.  One thread drives it."""
+
+    def __init__(self, batch, slots_per_class=4096, streams=2, staging_bytes=256 << 20):
+        L = _lib()
+        self.batch = batch
+        codes = batch.codes
+        arr = (ctypes.c_void_p * len(codes))(*[c.handle.value for c in codes])
+        h = L.polar_server_create(batch._h, arr, len(codes), int(slots_per_class), int(streams), int(staging_bytes))
+        if not h:
+            raise PolarError(L.polar_last_status(), "polar_server_create")
+        self._h = ctypes.c_void_p(h)
+        self._done = np.zeros(4096, np.int64)
+        self._keep = {}
+
+    def submit(self, code_index, llr, bits):
+        """llr: numpy array (host) or CUDA tensor (device, read in place)
+        [frames, N]; bits: numpy uint8 [frames, ceil(K/8)] filled when the
+        request completes.  Returns the request id, or None if the staging
+        memory is full (poll and retry)."""
+        rid = ctypes.c_int64(0)
+        if hasattr(llr, "data_ptr"):
+            ptr, on_dev, frames = llr.data_ptr(), 1, llr.shape[0]
+        else:
+            llr = np.ascontiguousarray(llr)
+            ptr, on_dev, frames = llr.ctypes.data, 0, llr.shape[0]
+        rc = _lib().polar_server_submit(self._h, int(code_index), int(frames), ctypes.c_void_p(ptr), on_dev,
+                                        ctypes.c_void_p(bits.ctypes.data), ctypes.byref(rid))
+        if rc == EAGAIN:
+            return None
+        _check(rc, "polar_server_submit")
+        self._keep[rid.value] = (llr, bits)
+        return rid.value
+
+    def poll(self):
+        """Progress; returns the ids of requests completed by this call."""
+        n = ctypes.c_int(0)
+        _check(_lib().polar_server_poll(self._h, _np_ptr(self._done), self._done.shape[0], ctypes.byref(n)),
+               "polar_server_poll")
+        ids = [int(x) for x in self._done[:min(n.value, self._done.shape[0])]]
+        for i in ids:
+            self._keep.pop(i, None)
+        return ids
+
+    def pending(self):
+        w, a, f = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        _check(_lib().polar_server_pending(self._h, ctypes.byref(w), ctypes.byref(a), ctypes.byref(f)),
+               "polar_server_pending")
+        return w.value, a.value, f.value
+
+    def drain(self):
+        """Polls until nothing is waiting or in flight; returns completed ids."""
+        done = []
+        while True:
+            done += self.poll()
+            if self.pending() == (0, 0, 0) and not self._keep:
+                return done
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().polar_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -9,43 +9,13 @@
 #include <vector>
 
 #include "../../include/polar.h"
-#include "plan.h"
-#include "unrolled.h"
+#include "internal.h"
 
 namespace polar {
 int launch_decode(const uint32_t* ops, int nops, int log2n, int kbits, int llr_type, const void* llr, int nframes,
                   uint8_t* bits, void* trace, int waves_per_block, void* stream);
 int set_lds_limit(int llr_type, int bytes);
 }  // namespace polar
-
-struct polar_code {
-  polar::Plan plan;
-  int llr_type = POLAR_LLR_I8;
-  int kernel = POLAR_KERNEL_SCHEDULE;
-  bool prepared = false;
-  int device = -1;
-  uint32_t* d_ops = nullptr;
-  int nops = 0;
-  int waves_per_block = 1;
-  polar::UnrolledKernel unrolled;
-};
-
-struct polar_batch {
-  std::vector<polar::Plan> plans;  // copies of the codes' schedules
-  int llr_type = POLAR_LLR_I8;
-  int wave_bytes = 0;              // LDS slot of one wave: the largest code's need
-  int waves_per_simd = 1;          // occupancy the generated kernel's registers are held to
-  bool prepared = false;
-  int device = -1;
-  int cus = 0;
-  hipModule_t module = nullptr;
-  hipFunction_t fn = nullptr;
-  int waves_per_block = 4;
-  int blocks = 0;
-  unsigned long long* d_desc = nullptr;  // descriptors from polar_batch_set_frames
-  int desc_cap = 0;
-  int nframes = 0;
-};
 
 namespace {
 
@@ -96,6 +66,8 @@ polar_code* make_code(int n, std::vector<uint8_t>&& frozen) {
 }
 
 }  // namespace
+
+polar_status polar_set_status(polar_status s) { return set(s); }
 
 extern "C" {
 
@@ -233,6 +205,7 @@ const char* polar_strerror(polar_status s) {
     case POLAR_EDEVICE: return "device error";
     case POLAR_ESTATE: return "invalid state";
     case POLAR_ECOMPILE: return "kernel compilation failed";
+    case POLAR_EAGAIN: return "no room right now; poll and retry";
   }
   return "unknown status";
 }

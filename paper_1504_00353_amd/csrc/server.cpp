@@ -1,0 +1,434 @@
+// Continuous-batching request server over a prepared polar_batch (C ABI in
+// include/polar.h, polar_server_*).
+//
+// Requests (1..n frames of one code; host LLRs in, host bits out) are
+// admitted first come, first served as soon as device slots for all their
+// frames are free.  Each frame-length class (one per distinct N among the
+// batch's codes) owns a ring of fixed-size frame slots inside one device LLR
+// pool and one device bits pool, so an admitted request holds one contiguous
+// slot range: one host-to-device copy per request in, one copy out.
+//
+// polar_server_poll() does all the work on the caller's thread: it retires
+// finished steps (their results are already in pinned host memory), admits
+// waiting requests, and launches a new step over every admitted frame not
+// yet launched, as long as a stream is free.  A step is the new requests'
+// LLR copies, the frame descriptors, one persistent batch decode, the result
+// copies and an event, all on one of the server's streams; a step overlaps
+// the one before it on the device, and requests that arrive while a step
+// runs join the next one.
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <deque>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+// Ring of n slots: allocation at the head, release in any order, the tail
+// advancing over released ranges.  Ranges never wrap (an end gap too small
+// for a request is skipped and counted as used until the tail passes it).
+struct Ring {
+  int n = 0, head = 0, tail = 0, used = 0;
+  std::vector<int> len;  // at a range start: its length; negated once released
+  std::vector<int> gap;  // at a skipped end gap start: its length
+
+  void init(int slots) {
+    n = slots;
+    head = tail = used = 0;
+    len.assign(slots, 0);
+    gap.assign(slots, 0);
+  }
+  int take(int k) {
+    const int s = head;
+    len[s] = k;
+    head += k;
+    if (head == n) head = 0;
+    used += k;
+    return s;
+  }
+  int alloc(int k) {
+    if (k <= 0 || k > n || used + k > n) return -1;
+    if (used == 0) head = tail = 0;
+    if (head >= tail) {
+      if (n - head >= k) return take(k);
+      if (tail >= k) {  // skip the end gap, continue at the front
+        const int g = n - head;
+        gap[head] = g;
+        used += g;
+        head = 0;
+        return take(k);
+      }
+      return -1;
+    }
+    return tail - head >= k ? take(k) : -1;
+  }
+  void release(int s) {
+    len[s] = -len[s];
+    while (used > 0) {
+      if (gap[tail] > 0) {
+        used -= gap[tail];
+        gap[tail] = 0;
+        tail = 0;
+      } else if (len[tail] < 0) {
+        const int k = -len[tail];
+        len[tail] = 0;
+        used -= k;
+        tail += k;
+        if (tail == n) tail = 0;
+      } else {
+        break;
+      }
+    }
+  }
+};
+
+struct SizeClass {
+  int n = 0;                // frame length
+  int llr_bytes = 0;        // bytes of one LLR slot
+  int bits_bytes = 0;       // bytes of one bits slot (largest ceil(K/8) of the class)
+  size_t llr_base = 0;      // byte offset of slot 0 in the LLR pool
+  size_t bits_base = 0;     // byte offset of slot 0 in the bits pool
+  Ring ring;
+};
+
+struct Request {
+  int code = 0, cls = 0, nframes = 0;
+  int slot = -1;            // first slot of its range in the class ring
+  const uint8_t* dev_llr = nullptr;  // LLRs already in device memory (else staged)
+  uint8_t* bits = nullptr;  // caller's host output
+  size_t stage_off = 0;     // its LLR copy in the pinned staging ring
+  size_t stage_len = 0;     // bytes taken there, including a skipped end gap
+  size_t stage_end = 0;     // end of its bytes in the ring
+};
+
+struct Step {
+  hipEvent_t done = nullptr;
+  int stream = 0;
+  std::vector<int64_t> reqs;
+};
+
+}  // namespace
+
+struct polar_server {
+  const polar_batch* batch = nullptr;
+  int elem = 1;
+  std::vector<int> code_n, code_rb, code_cls;
+  std::vector<SizeClass> cls;
+  uint8_t* d_llr = nullptr;
+  uint8_t* d_bits = nullptr;
+  uint8_t* h_bits = nullptr;  // pinned mirror of the bits pool
+  uint8_t* h_stage = nullptr;  // pinned staging ring for request LLRs
+  size_t stage_size = 0, stage_head = 0, stage_tail = 0, stage_used = 0;
+  uint64_t* d_desc = nullptr;  // one descriptor region per stream
+  uint64_t* h_desc = nullptr;
+  int desc_cap = 0;            // frames one step can carry
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  std::vector<bool> busy;
+  std::deque<int64_t> waiting;   // submitted, not yet admitted
+  std::deque<int64_t> admitted;  // admitted, not yet launched
+  std::deque<Step> inflight;
+  std::unordered_map<int64_t, Request> reqs;
+  int64_t next_id = 1;
+};
+
+namespace {
+
+void free_server(polar_server* s) {
+  for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  if (s->d_llr) (void)hipFree(s->d_llr);
+  if (s->d_bits) (void)hipFree(s->d_bits);
+  if (s->d_desc) (void)hipFree(s->d_desc);
+  if (s->h_bits) (void)hipHostFree(s->h_bits);
+  if (s->h_stage) (void)hipHostFree(s->h_stage);
+  if (s->h_desc) (void)hipHostFree(s->h_desc);
+  delete s;
+}
+
+// FIFO staging allocation (requests are staged, launched and retired in
+// submission order, so their staging is released in the same order).
+bool stage_alloc(polar_server* s, size_t bytes, size_t* off, size_t* taken) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (bytes > s->stage_size || s->stage_used + bytes > s->stage_size) return false;
+  if (s->stage_used == 0) s->stage_head = s->stage_tail = 0;
+  if (s->stage_head >= s->stage_tail) {
+    if (s->stage_size - s->stage_head >= bytes) {
+      *off = s->stage_head;
+      *taken = bytes;
+    } else if (s->stage_tail >= bytes) {
+      *off = 0;
+      *taken = bytes + (s->stage_size - s->stage_head);  // the skipped end gap goes with it
+    } else {
+      return false;
+    }
+  } else if (s->stage_tail - s->stage_head >= bytes) {
+    *off = s->stage_head;
+    *taken = bytes;
+  } else {
+    return false;
+  }
+  s->stage_head = *off + bytes;
+  if (s->stage_head == s->stage_size) s->stage_head = 0;
+  s->stage_used += *taken;
+  return true;
+}
+
+void stage_release(polar_server* s, const Request& r) {
+  s->stage_used -= r.stage_len;
+  s->stage_tail = r.stage_end == s->stage_size ? 0 : r.stage_end;
+  if (s->stage_used == 0) s->stage_head = s->stage_tail = 0;
+}
+
+// Moves waiting requests to admitted while their slots fit (FIFO).
+void admit(polar_server* s) {
+  while (!s->waiting.empty()) {
+    Request& r = s->reqs[s->waiting.front()];
+    const int slot = s->cls[r.cls].ring.alloc(r.nframes);
+    if (slot < 0) break;
+    r.slot = slot;
+    s->admitted.push_back(s->waiting.front());
+    s->waiting.pop_front();
+  }
+}
+
+polar_status launch(polar_server* s) {
+  if (s->admitted.empty()) return POLAR_OK;
+  int st = -1;
+  for (size_t i = 0; i < s->busy.size(); ++i)
+    if (!s->busy[i]) {
+      st = (int)i;
+      break;
+    }
+  if (st < 0) return POLAR_OK;
+  hipStream_t stream = s->streams[st];
+  uint64_t* hd = s->h_desc + 2 * (size_t)s->desc_cap * st;
+  uint64_t* dd = s->d_desc + 2 * (size_t)s->desc_cap * st;
+  Step step;
+  step.stream = st;
+  int nd = 0;
+  while (!s->admitted.empty()) {
+    const int64_t id = s->admitted.front();
+    Request& r = s->reqs[id];
+    if (nd + r.nframes > s->desc_cap) break;
+    const SizeClass& c = s->cls[r.cls];
+    const size_t llr_off = c.llr_base + (size_t)r.slot * c.llr_bytes;
+    const size_t bits_off = c.bits_base + (size_t)r.slot * c.bits_bytes;
+    // LLR element offset from the pool base: the request's slot for staged
+    // requests; for requests already in device memory, the signed distance
+    // to the caller's buffer (the kernel's 64-bit address sum wraps to it)
+    int64_t first;
+    if (r.dev_llr) {
+      first = (int64_t)((intptr_t)r.dev_llr - (intptr_t)s->d_llr) / s->elem;
+    } else {
+      first = (int64_t)(llr_off / (size_t)s->elem);
+      if (hipMemcpyAsync(s->d_llr + llr_off, s->h_stage + r.stage_off, (size_t)r.nframes * c.llr_bytes,
+                         hipMemcpyHostToDevice, stream) != hipSuccess)
+        return POLAR_EDEVICE;
+    }
+    for (int j = 0; j < r.nframes; ++j) {
+      hd[2 * nd] = (uint64_t)r.code | ((uint64_t)(bits_off + (size_t)j * c.bits_bytes) << 8);
+      hd[2 * nd + 1] = (uint64_t)(first + (int64_t)j * c.n);
+      ++nd;
+    }
+    step.reqs.push_back(id);
+    s->admitted.pop_front();
+  }
+  if (nd == 0) return POLAR_OK;
+  if (hipMemcpyAsync(dd, hd, (size_t)nd * 16, hipMemcpyHostToDevice, stream) != hipSuccess) return POLAR_EDEVICE;
+  if (polar_batch_decode_desc(s->batch, dd, nd, s->d_llr, s->d_bits, stream) != POLAR_OK) return POLAR_EDEVICE;
+  for (int64_t id : step.reqs) {
+    const Request& r = s->reqs[id];
+    const SizeClass& c = s->cls[r.cls];
+    const size_t bits_off = c.bits_base + (size_t)r.slot * c.bits_bytes;
+    if (hipMemcpyAsync(s->h_bits + bits_off, s->d_bits + bits_off, (size_t)r.nframes * c.bits_bytes,
+                       hipMemcpyDeviceToHost, stream) != hipSuccess)
+      return POLAR_EDEVICE;
+  }
+  step.done = s->events[st];
+  if (hipEventRecord(step.done, stream) != hipSuccess) return POLAR_EDEVICE;
+  s->busy[st] = true;
+  s->inflight.push_back(std::move(step));
+  return POLAR_OK;
+}
+
+// Retires finished steps in launch order; appends their request ids.
+polar_status retire(polar_server* s, int64_t* done, int cap, int* ndone) {
+  while (!s->inflight.empty()) {
+    Step& step = s->inflight.front();
+    const hipError_t q = hipEventQuery(step.done);
+    if (q == hipErrorNotReady) break;
+    if (q != hipSuccess) return POLAR_EDEVICE;
+    for (int64_t id : step.reqs) {
+      auto it = s->reqs.find(id);
+      Request& r = it->second;
+      const SizeClass& c = s->cls[r.cls];
+      const int rb = s->code_rb[r.code];
+      const uint8_t* src = s->h_bits + c.bits_base + (size_t)r.slot * c.bits_bytes;
+      for (int j = 0; j < r.nframes; ++j) memcpy(r.bits + (size_t)j * rb, src + (size_t)j * c.bits_bytes, rb);
+      s->cls[r.cls].ring.release(r.slot);
+      if (!r.dev_llr) stage_release(s, r);
+      if (*ndone < cap && done) done[*ndone] = id;
+      ++*ndone;
+      s->reqs.erase(it);
+    }
+    s->busy[step.stream] = false;
+    s->inflight.pop_front();
+  }
+  return POLAR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+polar_server* polar_server_create(const polar_batch* batch, const polar_code* const* codes, int ncodes,
+                                  int slots_per_class, int streams, size_t staging_bytes) {
+  if (!batch || !codes || ncodes < 1 || ncodes != (int)batch->plans.size() || slots_per_class < 1 || streams < 1 ||
+      streams > 8 || staging_bytes < 4096 || !batch->prepared) {
+    polar_set_status(!batch || (batch && !batch->prepared) ? (batch ? POLAR_ESTATE : POLAR_EINVAL) : POLAR_EINVAL);
+    return nullptr;
+  }
+  polar_server* s = new (std::nothrow) polar_server;
+  if (!s) {
+    polar_set_status(POLAR_ENOMEM);
+    return nullptr;
+  }
+  polar_status st = POLAR_OK;
+  try {
+    s->batch = batch;
+    s->elem = batch->llr_type == POLAR_LLR_F32 ? 4 : 1;
+    for (int i = 0; i < ncodes; ++i) {
+      if (!codes[i] || codes[i]->plan.n != batch->plans[i].n || codes[i]->plan.frozen != batch->plans[i].frozen) {
+        st = POLAR_EINVAL;
+        break;
+      }
+      s->code_n.push_back(codes[i]->plan.n);
+      s->code_rb.push_back((codes[i]->plan.k + 7) / 8);
+      int c = -1;
+      for (size_t j = 0; j < s->cls.size(); ++j)
+        if (s->cls[j].n == codes[i]->plan.n) c = (int)j;
+      if (c < 0) {
+        SizeClass sc;
+        sc.n = codes[i]->plan.n;
+        sc.llr_bytes = sc.n * s->elem;
+        s->cls.push_back(sc);
+        c = (int)s->cls.size() - 1;
+      }
+      s->code_cls.push_back(c);
+      s->cls[c].bits_bytes = std::max(s->cls[c].bits_bytes, (codes[i]->plan.k + 7) / 8);
+    }
+    if (st == POLAR_OK) {
+      size_t llr_total = 0, bits_total = 0;
+      for (SizeClass& c : s->cls) {
+        c.bits_bytes = (c.bits_bytes + 15) & ~15;
+        c.llr_base = llr_total;
+        c.bits_base = bits_total;
+        llr_total += (size_t)slots_per_class * c.llr_bytes;
+        bits_total += (size_t)slots_per_class * c.bits_bytes;
+        c.ring.init(slots_per_class);
+      }
+      s->desc_cap = slots_per_class * (int)s->cls.size();
+      s->stage_size = staging_bytes;
+      if (hipMalloc((void**)&s->d_llr, llr_total) != hipSuccess ||
+          hipMalloc((void**)&s->d_bits, bits_total) != hipSuccess ||
+          hipMalloc((void**)&s->d_desc, (size_t)streams * s->desc_cap * 16) != hipSuccess ||
+          hipHostMalloc((void**)&s->h_bits, bits_total, 0) != hipSuccess ||
+          hipHostMalloc((void**)&s->h_stage, staging_bytes, 0) != hipSuccess ||
+          hipHostMalloc((void**)&s->h_desc, (size_t)streams * s->desc_cap * 16, 0) != hipSuccess)
+        st = POLAR_ENOMEM;
+      for (int i = 0; i < streams && st == POLAR_OK; ++i) {
+        hipStream_t hs = nullptr;
+        hipEvent_t ev = nullptr;
+        if (hipStreamCreateWithFlags(&hs, hipStreamNonBlocking) != hipSuccess) {
+          st = POLAR_EDEVICE;
+          break;
+        }
+        s->streams.push_back(hs);
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+          st = POLAR_EDEVICE;
+          break;
+        }
+        s->events.push_back(ev);
+        s->busy.push_back(false);
+      }
+    }
+  } catch (const std::bad_alloc&) {
+    st = POLAR_ENOMEM;
+  }
+  if (st != POLAR_OK) {
+    free_server(s);
+    polar_set_status(st);
+    return nullptr;
+  }
+  polar_set_status(POLAR_OK);
+  return s;
+}
+
+polar_status polar_server_submit(polar_server* s, int code_index, int nframes, const void* llr, int llr_on_device,
+                                 uint8_t* bits, int64_t* id) {
+  if (!s || code_index < 0 || code_index >= (int)s->code_n.size() || nframes < 1 || !llr || !bits || !id)
+    return polar_set_status(POLAR_EINVAL);
+  const SizeClass& c = s->cls[s->code_cls[code_index]];
+  if (nframes > c.ring.n) return polar_set_status(POLAR_EINVAL);  // could never be admitted
+  if (llr_on_device && ((uintptr_t)llr % (uintptr_t)s->elem) != 0) return polar_set_status(POLAR_EINVAL);
+  const size_t bytes = (size_t)nframes * c.llr_bytes;
+  Request r;
+  r.code = code_index;
+  r.cls = s->code_cls[code_index];
+  r.nframes = nframes;
+  r.bits = bits;
+  if (llr_on_device) {
+    r.dev_llr = (const uint8_t*)llr;
+  } else {
+    if (!stage_alloc(s, bytes, &r.stage_off, &r.stage_len)) return polar_set_status(POLAR_EAGAIN);
+    r.stage_end = r.stage_off + ((bytes + 255) & ~(size_t)255);
+    memcpy(s->h_stage + r.stage_off, llr, bytes);
+  }
+  try {
+    const int64_t rid = s->next_id++;
+    s->reqs.emplace(rid, r);
+    s->waiting.push_back(rid);
+    *id = rid;
+  } catch (const std::bad_alloc&) {
+    return polar_set_status(POLAR_ENOMEM);
+  }
+  return polar_set_status(POLAR_OK);
+}
+
+polar_status polar_server_poll(polar_server* s, int64_t* done_ids, int cap, int* ndone) {
+  if (!s || cap < 0 || !ndone) return polar_set_status(POLAR_EINVAL);
+  *ndone = 0;
+  try {
+    polar_status st = retire(s, done_ids, cap, ndone);
+    if (st != POLAR_OK) return polar_set_status(st);
+    admit(s);
+    st = launch(s);
+    if (st != POLAR_OK) return polar_set_status(st);
+  } catch (const std::bad_alloc&) {
+    return polar_set_status(POLAR_ENOMEM);
+  }
+  return polar_set_status(POLAR_OK);
+}
+
+polar_status polar_server_pending(const polar_server* s, int* waiting, int* admitted, int* inflight_steps) {
+  if (!s) return polar_set_status(POLAR_EINVAL);
+  if (waiting) *waiting = (int)s->waiting.size();
+  if (admitted) *admitted = (int)s->admitted.size();
+  if (inflight_steps) *inflight_steps = (int)s->inflight.size();
+  return polar_set_status(POLAR_OK);
+}
+
+void polar_server_destroy(polar_server* s) {
+  if (!s) return;
+  for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+  free_server(s);
+}
+
+}  // extern "C"
