@@ -12,7 +12,9 @@ Gb/s single-core figure for this code.  Prints one JSON line:
                over the decode kernel's mean duration vs 8 TB/s;
   cpu_baseline the CPU oracle on a bounded sample on this host's cores;
   mixed_batch  the 65,536-frame mixed-code workload in one persistent,
-               autotuned launch (information Gb/s, launch time, FER).
+               autotuned launch (information Gb/s, launch time, FER);
+  serving      the continuous-batching server under Poisson arrivals at
+               10/50/90% of the batch capacity: Gb/s and p50/p99 latency.
 """
 import argparse
 import hashlib
@@ -155,6 +157,80 @@ def mixed_batch_bench(steps, pool_frames=4096, frames=65536, seed=3):
             "fer": round(fe / frames, 5), "launch_shape": shape}
 
 
+def serving_bench(seconds=1.0, loads=(0.1, 0.5, 0.9), seed=4, pool=64, capacity_frames=16384):
+    """Requests of 1..64 frames (code uniform over N in {1024, 4096, 32768} x
+    R in {0.5, ..., 0.9}, Eb/N0 uniform 2-5 dB) with Poisson arrivals at
+    fractions of the measured batch capacity, replayed by the library's
+    native load generator against the continuous-batching server; LLRs and
+    results device-resident.  Latency = arrival -> completion seen by the
+    server's poll loop."""
+    import torch
+    from paper_1504_00353_amd import Batch, Code, Server, synth, workloads as W
+    codes = [Code(n, k, d, llr="i8", prepare=False) for n, k, d in W.SERVING["codes"]]
+    batch = Batch(codes)
+    rng = np.random.default_rng(seed)
+    # device pool: `pool` channel frames per code, back to back
+    offs, parts, o = [], [], 0
+    for c, code in enumerate(codes):
+        idx = np.arange(pool) + 100000 * c
+        bits = synth.info_bits(seed, idx, code.k)
+        x = synth.unpack_bits(code.encode(synth.pack_bits(bits)), code.n)
+        eb = rng.uniform(*W.SERVING["ebn0_db"], size=pool)
+        parts.append(synth.quantize6(synth.awgn_llr(x, synth.noise(seed, idx, code.n), eb, code.k / code.n)).ravel())
+        offs.append(o)
+        o += pool * code.n
+    flat = torch.from_numpy(np.concatenate(parts)).cuda()
+    base = flat.data_ptr()
+    ns = np.array([c.n for c in codes])
+    rbs = np.array([c.row_bytes for c in codes])
+    ks = np.array([c.k for c in codes])
+    # batch capacity on this mix (frames/s), autotuned
+    cidx = rng.integers(0, len(codes), size=capacity_frames).astype(np.int32)
+    start = rng.integers(0, pool, size=capacity_frames)
+    lo = np.array([offs[c] + s * ns[c] for c, s in zip(cidx, start)], np.int64)
+    bo = np.concatenate([[0], np.cumsum(rbs[cidx])[:-1]]).astype(np.int64)
+    out = torch.zeros(int(rbs[cidx].sum()), dtype=torch.uint8, device="cuda")
+    batch.set_frames(cidx, lo, bo)
+    batch.tune(flat, out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(5):
+        e0.record()
+        batch.decode(flat, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    cap_fps = capacity_frames / (float(np.median(ts)) / 1e3)
+    mean_frames = 32.5
+    srv = Server(batch, slots_per_class=8192, streams=2)
+    ring = 8192  # result regions reused round robin (results of finished requests get overwritten)
+    out_ring = torch.zeros(ring * 64 * int(rbs.max()), dtype=torch.uint8, device="cuda")
+    results = []
+    for load in loads:
+        rate = load * cap_fps / mean_frames
+        n = max(int(rate * seconds), 50)
+        arrival = np.cumsum(rng.exponential(1.0 / rate, size=n))
+        c = rng.integers(0, len(codes), size=n).astype(np.int32)
+        f = rng.integers(1, 65, size=n).astype(np.int32)
+        s0 = rng.integers(0, pool - f + 1)
+        lp = (base + np.array(offs, np.int64)[c] + s0 * ns[c]).astype(np.uint64)
+        bp = (out_ring.data_ptr() + (np.arange(n) % ring) * 64 * int(rbs.max())).astype(np.uint64)
+        done = srv.run_trace(arrival, c, f, lp, bp)
+        torch.cuda.synchronize()
+        lat = (done - arrival) * 1e6
+        span = float(done.max() - arrival[0])
+        info = float((ks[c] * f).sum())
+        results.append({"offered_load": load, "requests": n, "frames": int(f.sum()),
+                        "offered_frames_per_s": round(load * cap_fps), "value": round(info / span / 1e9, 3),
+                        "unit": "Gbps",
+                        "latency_us": {"p50": round(percentile(lat, 50), 1), "p99": round(percentile(lat, 99), 1)},
+                        "frame_latency_us": {"p50": round(float(np.percentile(np.repeat(lat, f), 50)), 1),
+                                             "p99": round(float(np.percentile(np.repeat(lat, f), 99)), 1)}})
+    srv.close()
+    return {"batch_capacity_frames_per_s": round(cap_fps), "capacity_launch": batch.launch_shape(),
+            "loads": results, "what": "Poisson arrivals, 1..64 frames per request, device-resident LLRs and results"}
+
+
 def percentile(v, p):
     return float(np.percentile(np.asarray(v, np.float64), p))
 
@@ -189,6 +265,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-code batch measurement")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-server measurement")
+    ap.add_argument("--serving-seconds", type=float, default=1.0)
     ap.add_argument("--kernel", choices=["unrolled", "schedule"], default="unrolled",
                     help="generated per-code kernel (default) or the schedule-interpreting one")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -310,6 +388,8 @@ def main():
     }
     if not args.no_mixed and args.kernel == "unrolled":
         result["mixed_batch"] = mixed_batch_bench(max(args.steps // 2, 3))
+    if not args.no_serving and args.kernel == "unrolled":
+        result["serving"] = serving_bench(args.serving_seconds)
     if not args.no_cpu:
         done, dt, threads, one_core_us = cpu_baseline(frozen, llr_np, args.cpu_seconds)
         result["cpu_baseline"] = {"value": round(done * k / dt / 1e9, 5), "unit": "Gbps", "cores": threads,

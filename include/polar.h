@@ -259,19 +259,35 @@ typedef struct polar_server polar_server; /* opaque; owned by the library */
 polar_server* polar_server_create(const polar_batch* batch, const polar_code* const* codes, int ncodes,
                                   int slots_per_class, int streams, size_t staging_bytes);
 
+/* Where the buffers of a request live (flags for polar_server_submit). */
+enum { POLAR_SERVER_LLR_DEVICE = 1, POLAR_SERVER_BITS_DEVICE = 2 };
+
 /* Queues a request of nframes frames of code code_index (an index into
- * the batch's codes).  llr: [nframes][N] LLRs of the batch's type, either
- * host memory (llr_on_device = 0: copied to pinned staging before the call
- * returns, then to a device slot by the request's step) or device memory
- * on the server's device (llr_on_device = 1: read in place, no copy; it
- * must stay valid until the request is reported done).  bits: host memory
- * [nframes][ceil(K/8)], written by the poll that reports the request done;
- * it must stay valid until then.  *id receives the request id (> 0).
- * Errors: POLAR_EINVAL (bad arguments, or more frames than the code's
- * length class has slots), POLAR_EAGAIN (staging memory full: poll, then
- * submit again). */
-polar_status polar_server_submit(polar_server* server, int code_index, int nframes, const void* llr,
-                                 int llr_on_device, uint8_t* bits, int64_t* id);
+ * the batch's codes).  llr: [nframes][N] LLRs of the batch's type in host
+ * memory (copied to pinned staging before the call returns, then to a
+ * device slot by the request's step) or, with POLAR_SERVER_LLR_DEVICE in
+ * `where`, in device memory of the server's device (read in place, no
+ * copy).  bits: [nframes][ceil(K/8)] results, in host memory (written by
+ * the poll that reports the request done) or, with
+ * POLAR_SERVER_BITS_DEVICE, in device memory (written in place by the
+ * decode).  Buffers must stay valid until the request is reported done.
+ * *id receives the request id (> 0).  Errors: POLAR_EINVAL (bad arguments,
+ * or more frames than the code's length class has slots), POLAR_EAGAIN
+ * (staging memory full: poll, then submit again). */
+polar_status polar_server_submit(polar_server* server, int code_index, int nframes, const void* llr, int where,
+                                 uint8_t* bits, int64_t* id);
+
+/* Replays a timed request trace against the server on the calling thread,
+ * as a load generator: request i (code code_index[i], nframes[i] frames,
+ * device LLRs llr[i], device results bits[i]) is submitted once
+ * arrival_s[i] seconds have passed since the call began (arrival_s
+ * non-decreasing), and the server is polled continuously;
+ * completion_s[i] receives the time (same clock) at which a poll saw it
+ * done.  Returns when every request is done.  Errors: POLAR_EINVAL,
+ * POLAR_EDEVICE. */
+polar_status polar_server_run_trace(polar_server* server, int nreq, const double* arrival_s,
+                                    const int32_t* code_index, const int32_t* nframes, const void* const* llr,
+                                    uint8_t* const* bits, double* completion_s);
 
 /* Makes progress without blocking: retires finished steps (writing their
  * requests' bits), admits waiting requests, launches a step.  Writes the

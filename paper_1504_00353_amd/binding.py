@@ -23,7 +23,7 @@ EXPORTS = [
     "polar_last_message", "polar_batch_create", "polar_batch_build_kernel", "polar_batch_prepare",
     "polar_batch_set_frames", "polar_batch_decode", "polar_batch_decode_desc", "polar_batch_tune",
     "polar_batch_launch_shape", "polar_batch_destroy", "polar_server_create", "polar_server_submit",
-    "polar_server_poll", "polar_server_pending", "polar_server_destroy",
+    "polar_server_poll", "polar_server_pending", "polar_server_destroy", "polar_server_run_trace",
 ]
 
 
@@ -86,6 +86,7 @@ def _lib():
         L.polar_server_pending.argtypes = [P, P, P, P]
         L.polar_server_destroy.argtypes = [P]
         L.polar_server_destroy.restype = None
+        L.polar_server_run_trace.argtypes = [P, I, P, P, P, P, P, P]
         _L = L
     return _L
 
@@ -301,17 +302,25 @@ class Server:
 
     def submit(self, code_index, llr, bits):
         """llr: numpy array (host) or CUDA tensor (device, read in place)
-        [frames, N]; bits: numpy uint8 [frames, ceil(K/8)] filled when the
-        request completes.  Returns the request id, or None if the staging
-        memory is full (poll and retry)."""
+        [frames, N]; bits: numpy uint8 [frames, ceil(K/8)] (filled when the
+        request completes) or a CUDA uint8 tensor (written in place).
+        Returns the request id, or None if the staging memory is full
+        (poll and retry)."""
         rid = ctypes.c_int64(0)
+        where = 0
         if hasattr(llr, "data_ptr"):
-            ptr, on_dev, frames = llr.data_ptr(), 1, llr.shape[0]
+            ptr, frames = llr.data_ptr(), llr.shape[0]
+            where |= 1
         else:
             llr = np.ascontiguousarray(llr)
-            ptr, on_dev, frames = llr.ctypes.data, 0, llr.shape[0]
-        rc = _lib().polar_server_submit(self._h, int(code_index), int(frames), ctypes.c_void_p(ptr), on_dev,
-                                        ctypes.c_void_p(bits.ctypes.data), ctypes.byref(rid))
+            ptr, frames = llr.ctypes.data, llr.shape[0]
+        if hasattr(bits, "data_ptr"):
+            bptr = bits.data_ptr()
+            where |= 2
+        else:
+            bptr = bits.ctypes.data
+        rc = _lib().polar_server_submit(self._h, int(code_index), int(frames), ctypes.c_void_p(ptr), where,
+                                        ctypes.c_void_p(bptr), ctypes.byref(rid))
         if rc == EAGAIN:
             return None
         _check(rc, "polar_server_submit")
@@ -327,6 +336,20 @@ class Server:
         for i in ids:
             self._keep.pop(i, None)
         return ids
+
+    def run_trace(self, arrival_s, code_index, nframes, llr_ptrs, bits_ptrs):
+        """Native load generator: submits request i at arrival_s[i] seconds
+        (device LLR / bits addresses), polls until all are done; returns
+        the completion times (seconds, same clock)."""
+        a = np.ascontiguousarray(arrival_s, np.float64)
+        c = np.ascontiguousarray(code_index, np.int32)
+        f = np.ascontiguousarray(nframes, np.int32)
+        lp = np.ascontiguousarray(llr_ptrs, np.uint64)
+        bp = np.ascontiguousarray(bits_ptrs, np.uint64)
+        done = np.zeros(a.shape[0], np.float64)
+        _check(_lib().polar_server_run_trace(self._h, a.shape[0], _np_ptr(a), _np_ptr(c), _np_ptr(f), _np_ptr(lp),
+                                             _np_ptr(bp), _np_ptr(done)), "polar_server_run_trace")
+        return done
 
     def pending(self):
         w, a, f = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)

@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <deque>
 #include <new>
 #include <unordered_map>
@@ -101,7 +102,8 @@ struct Request {
   int code = 0, cls = 0, nframes = 0;
   int slot = -1;            // first slot of its range in the class ring
   const uint8_t* dev_llr = nullptr;  // LLRs already in device memory (else staged)
-  uint8_t* bits = nullptr;  // caller's host output
+  uint8_t* bits = nullptr;  // caller's output: host memory, or device memory if dev_bits
+  bool dev_bits = false;
   size_t stage_off = 0;     // its LLR copy in the pinned staging ring
   size_t stage_len = 0;     // bytes taken there, including a skipped end gap
   size_t stage_end = 0;     // end of its bytes in the ring
@@ -232,8 +234,13 @@ polar_status launch(polar_server* s) {
                          hipMemcpyHostToDevice, stream) != hipSuccess)
         return POLAR_EDEVICE;
     }
+    // output: the request's bits slots, or the caller's device buffer
+    // (signed distance from the bits pool base)
+    const int rb = s->code_rb[r.code];
+    const int64_t out0 = r.dev_bits ? (int64_t)((intptr_t)r.bits - (intptr_t)s->d_bits) : (int64_t)bits_off;
+    const int64_t ostep = r.dev_bits ? rb : c.bits_bytes;
     for (int j = 0; j < r.nframes; ++j) {
-      hd[2 * nd] = (uint64_t)r.code | ((uint64_t)(bits_off + (size_t)j * c.bits_bytes) << 8);
+      hd[2 * nd] = (uint64_t)r.code | ((uint64_t)(out0 + (int64_t)j * ostep) << 8);
       hd[2 * nd + 1] = (uint64_t)(first + (int64_t)j * c.n);
       ++nd;
     }
@@ -243,13 +250,35 @@ polar_status launch(polar_server* s) {
   if (nd == 0) return POLAR_OK;
   if (hipMemcpyAsync(dd, hd, (size_t)nd * 16, hipMemcpyHostToDevice, stream) != hipSuccess) return POLAR_EDEVICE;
   if (polar_batch_decode_desc(s->batch, dd, nd, s->d_llr, s->d_bits, stream) != POLAR_OK) return POLAR_EDEVICE;
-  for (int64_t id : step.reqs) {
-    const Request& r = s->reqs[id];
-    const SizeClass& c = s->cls[r.cls];
-    const size_t bits_off = c.bits_base + (size_t)r.slot * c.bits_bytes;
-    if (hipMemcpyAsync(s->h_bits + bits_off, s->d_bits + bits_off, (size_t)r.nframes * c.bits_bytes,
-                       hipMemcpyDeviceToHost, stream) != hipSuccess)
-      return POLAR_EDEVICE;
+  // results to pinned host memory: one copy per slot range of each length
+  // class touched by the step (ring ranges are contiguous unless they wrap)
+  for (size_t ci = 0; ci < s->cls.size(); ++ci) {
+    int lo = -1, hi = -1;
+    bool wrapped = false;
+    for (int64_t id : step.reqs) {
+      const Request& r = s->reqs[id];
+      if (r.cls != (int)ci || r.dev_bits) continue;
+      if (lo >= 0 && r.slot < lo) wrapped = true;
+      if (lo < 0 || r.slot < lo) lo = r.slot;
+      hi = std::max(hi, r.slot + r.nframes);
+    }
+    if (lo < 0) continue;
+    const SizeClass& c = s->cls[ci];
+    if (wrapped) {  // copy each request's range
+      for (int64_t id : step.reqs) {
+        const Request& r = s->reqs[id];
+        if (r.cls != (int)ci || r.dev_bits) continue;
+        const size_t off = c.bits_base + (size_t)r.slot * c.bits_bytes;
+        if (hipMemcpyAsync(s->h_bits + off, s->d_bits + off, (size_t)r.nframes * c.bits_bytes,
+                           hipMemcpyDeviceToHost, stream) != hipSuccess)
+          return POLAR_EDEVICE;
+      }
+    } else {
+      const size_t off = c.bits_base + (size_t)lo * c.bits_bytes;
+      if (hipMemcpyAsync(s->h_bits + off, s->d_bits + off, (size_t)(hi - lo) * c.bits_bytes, hipMemcpyDeviceToHost,
+                         stream) != hipSuccess)
+        return POLAR_EDEVICE;
+    }
   }
   step.done = s->events[st];
   if (hipEventRecord(step.done, stream) != hipSuccess) return POLAR_EDEVICE;
@@ -258,8 +287,9 @@ polar_status launch(polar_server* s) {
   return POLAR_OK;
 }
 
-// Retires finished steps in launch order; appends their request ids.
-polar_status retire(polar_server* s, int64_t* done, int cap, int* ndone) {
+// Retires finished steps in launch order; appends their request ids (to
+// done while cap allows, and to all when given).
+polar_status retire(polar_server* s, int64_t* done, int cap, int* ndone, std::vector<int64_t>* all = nullptr) {
   while (!s->inflight.empty()) {
     Step& step = s->inflight.front();
     const hipError_t q = hipEventQuery(step.done);
@@ -271,10 +301,12 @@ polar_status retire(polar_server* s, int64_t* done, int cap, int* ndone) {
       const SizeClass& c = s->cls[r.cls];
       const int rb = s->code_rb[r.code];
       const uint8_t* src = s->h_bits + c.bits_base + (size_t)r.slot * c.bits_bytes;
-      for (int j = 0; j < r.nframes; ++j) memcpy(r.bits + (size_t)j * rb, src + (size_t)j * c.bits_bytes, rb);
+      if (!r.dev_bits)
+        for (int j = 0; j < r.nframes; ++j) memcpy(r.bits + (size_t)j * rb, src + (size_t)j * c.bits_bytes, rb);
       s->cls[r.cls].ring.release(r.slot);
       if (!r.dev_llr) stage_release(s, r);
       if (*ndone < cap && done) done[*ndone] = id;
+      if (all) all->push_back(id);
       ++*ndone;
       s->reqs.erase(it);
     }
@@ -371,8 +403,9 @@ polar_server* polar_server_create(const polar_batch* batch, const polar_code* co
   return s;
 }
 
-polar_status polar_server_submit(polar_server* s, int code_index, int nframes, const void* llr, int llr_on_device,
+polar_status polar_server_submit(polar_server* s, int code_index, int nframes, const void* llr, int where,
                                  uint8_t* bits, int64_t* id) {
+  const int llr_on_device = where & POLAR_SERVER_LLR_DEVICE;
   if (!s || code_index < 0 || code_index >= (int)s->code_n.size() || nframes < 1 || !llr || !bits || !id)
     return polar_set_status(POLAR_EINVAL);
   const SizeClass& c = s->cls[s->code_cls[code_index]];
@@ -384,6 +417,7 @@ polar_status polar_server_submit(polar_server* s, int code_index, int nframes, c
   r.cls = s->code_cls[code_index];
   r.nframes = nframes;
   r.bits = bits;
+  r.dev_bits = (where & POLAR_SERVER_BITS_DEVICE) != 0;
   if (llr_on_device) {
     r.dev_llr = (const uint8_t*)llr;
   } else {
@@ -411,6 +445,52 @@ polar_status polar_server_poll(polar_server* s, int64_t* done_ids, int cap, int*
     admit(s);
     st = launch(s);
     if (st != POLAR_OK) return polar_set_status(st);
+  } catch (const std::bad_alloc&) {
+    return polar_set_status(POLAR_ENOMEM);
+  }
+  return polar_set_status(POLAR_OK);
+}
+
+polar_status polar_server_run_trace(polar_server* s, int nreq, const double* arrival_s, const int32_t* code_index,
+                                    const int32_t* nframes, const void* const* llr, uint8_t* const* bits,
+                                    double* completion_s) {
+  if (!s || nreq < 0 || (nreq > 0 && (!arrival_s || !code_index || !nframes || !llr || !bits || !completion_s)))
+    return polar_set_status(POLAR_EINVAL);
+  typedef std::chrono::steady_clock clk;
+  const clk::time_point t0 = clk::now();
+  auto since = [&]() { return std::chrono::duration<double>(clk::now() - t0).count(); };
+  try {
+    std::unordered_map<int64_t, int> which;
+    std::vector<int64_t> done;
+    int next = 0, finished = 0;
+    while (finished < nreq) {
+      const double now = since();
+      while (next < nreq && arrival_s[next] <= now) {
+        int64_t id = 0;
+        const polar_status st = polar_server_submit(s, code_index[next], nframes[next], llr[next],
+                                                    POLAR_SERVER_LLR_DEVICE | POLAR_SERVER_BITS_DEVICE, bits[next], &id);
+        if (st != POLAR_OK) return st;
+        which[id] = next++;
+      }
+      done.clear();
+      int nd = 0;
+      polar_status st = retire(s, nullptr, 0, &nd, &done);
+      if (st != POLAR_OK) return polar_set_status(st);
+      admit(s);
+      st = launch(s);
+      if (st != POLAR_OK) return polar_set_status(st);
+      if (!done.empty()) {
+        const double t = since();
+        for (int64_t id : done) {
+          auto it = which.find(id);
+          if (it != which.end()) {
+            completion_s[it->second] = t;
+            which.erase(it);
+            ++finished;
+          }
+        }
+      }
+    }
   } catch (const std::bad_alloc&) {
     return polar_set_status(POLAR_ENOMEM);
   }

@@ -171,7 +171,8 @@ std::string batch_source(const std::vector<const Plan*>& plans, int llr_type, in
   }
   s += "}  // namespace\n\n";
   // Frame descriptor: two 64-bit words, [0] = code index | bits byte offset << 8,
-  // [1] = LLR offset in elements.  Each wave takes frames wave, wave + W, ...
+  // [1] = LLR offset in elements; both offsets signed.  Each wave takes
+  // frames wave, wave + W, ...
   s += "extern \"C\" __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(" +
        std::to_string(waves_per_simd) + "))) polar_batch(const unsigned long long* __restrict__ desc, int nframes, const " +
        chan + "* __restrict__ llr, uint8_t* __restrict__ bits, int wave_bytes) {\n";
@@ -185,7 +186,7 @@ std::string batch_source(const std::vector<const Plan*>& plans, int llr_type, in
   s += "    switch ((unsigned)(d0 & 255u)) {\n";
   for (size_t c = 0; c < plans.size(); ++c)
     s += "      case " + std::to_string(c) + ": dec_" + std::to_string(c) +
-         "(base, lane, llr + d1, bits + (d0 >> 8)); break;\n";
+         "(base, lane, llr + (long long)d1, bits + ((long long)d0 >> 8)); break;\n";
   s += "      default: break;\n    }\n  }\n}\n";
   return s;
 }
