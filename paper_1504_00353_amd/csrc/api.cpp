@@ -159,6 +159,9 @@ polar_status polar_prepare(polar_code* c) {
       std::string log;
       if (polar::unrolled_code_object(c->plan, c->llr_type, code, log) != 0) return set_msg(POLAR_ECOMPILE, log);
       if (polar::unrolled_load(code, c->unrolled) != 0) return set(POLAR_EDEVICE);
+      c->unrolled.wave_bytes = polar::unrolled_wave_bytes(c->plan, c->llr_type);
+      const int uw = lds_max / c->unrolled.wave_bytes;
+      wpb = uw < 1 ? 1 : (uw > 4 ? 4 : uw);
     } catch (const std::bad_alloc&) {
       return set(POLAR_ENOMEM);
     }
@@ -270,8 +273,7 @@ static polar_status decode_impl(const polar_code* c, const void* llr, int nframe
   if (((uintptr_t)llr & 3u) != 0) return set(POLAR_EINVAL);
   if (c->llr_type == POLAR_LLR_F32 && trace && ((uintptr_t)trace & 3u) != 0) return set(POLAR_EINVAL);
   const int rc = c->kernel == POLAR_KERNEL_UNROLLED
-                     ? polar::unrolled_launch(c->unrolled, c->plan.log2n, c->llr_type, llr, nframes, bits, trace,
-                                              c->waves_per_block, stream)
+                     ? polar::unrolled_launch(c->unrolled, llr, nframes, bits, trace, c->waves_per_block, stream)
                      : polar::launch_decode(c->d_ops, c->nops, c->plan.log2n, c->plan.k, c->llr_type, llr, nframes,
                                             bits, trace, c->waves_per_block, stream);
   return set(rc == 0 ? POLAR_OK : POLAR_EDEVICE);
@@ -290,6 +292,8 @@ polar_status polar_decode_trace(const polar_code* c, const void* llr, int nframe
 
 /* ------------------------------------------------------------------ batch */
 
+}  // extern "C"
+
 namespace {
 
 int batch_occupancy(int wave_bytes, int lds_per_cu) {
@@ -306,6 +310,8 @@ std::string batch_src(const polar_batch* b) {
 }
 
 }  // namespace
+
+extern "C" {
 
 polar_batch* polar_batch_create(const polar_code* const* codes, int ncodes) {
   if (!codes || ncodes < 1 || ncodes > 255) {
@@ -324,11 +330,9 @@ polar_batch* polar_batch_create(const polar_code* const* codes, int ncodes) {
   }
   try {
     b->llr_type = codes[0]->llr_type;
-    const int elem = b->llr_type == POLAR_LLR_F32 ? 4 : 1;
     for (int i = 0; i < ncodes; ++i) {
       b->plans.push_back(codes[i]->plan);
-      const int l2 = codes[i]->plan.log2n;
-      b->wave_bytes = std::max(b->wave_bytes, polar::wave_lds_bytes(l2, elem, polar::unrolled_nreg(l2, b->llr_type)));
+      b->wave_bytes = std::max(b->wave_bytes, polar::unrolled_wave_bytes(codes[i]->plan, b->llr_type));
     }
   } catch (const std::bad_alloc&) {
     delete b;

@@ -969,27 +969,34 @@ struct Dec {
 // (e >> 4) & 63, register 4 (e >> 10) + ((e >> 2) & 3), byte e & 3, so the
 // pair e, e + 2^(s-1) of f and g is always lane-local.
 // ---------------------------------------------------------------------------
-template <int L2N, int NREG>
+template <int TOP, int NREG>
 struct RegStages {
-  static constexpr bool has(int s) { return NREG > 0 && s <= L2N - 1 && s >= L2N - NREG; }
-  // first register of stage s: stage L2N-1 first, then the next lower
+  // register stages: TOP down to TOP - NREG + 1
+  static constexpr bool has(int s) { return NREG > 0 && s <= TOP && s > TOP - NREG; }
+  // first register of stage s: stage TOP first, then the next lower
   static constexpr int base(int s) {
     int b = 0;
-    for (int t = L2N - 1; t > s; --t) b += (1 << t) >> 8;
+    for (int t = TOP; t > s; --t) b += (1 << t) >> 8;
     return b;
   }
-  static constexpr int total() { return NREG > 0 ? base(L2N - NREG - 1) : 1; }
+  static constexpr int total() { return NREG > 0 ? base(TOP - NREG) : 1; }
 };
 
-template <class P, int L2N, int NREG>
+// VTOP = 1: the stage below the root (L2N-1) is never stored: the two ops
+// that read it (f/g/g_0R of each child of the root) recompute it from the
+// channel row with the root's op (fused_top), which frees its registers
+// for the next two stages and keeps a frame within 128 VGPRs and 8.2 KB of
+// LDS (N = 32768), four frames per SIMD.
+template <class P, int L2N, int NREG, int VTOP = 0>
 struct DecU : Dec<P> {
   typedef Dec<P> B;
-  typedef RegStages<L2N, NREG> R;
-  static_assert(NREG == 0 || (P::ELEM == 1 && L2N - NREG >= 11), "register stages: int8, >= 2^11 LLRs");
+  typedef RegStages<L2N - 1 - VTOP, NREG> R;
+  static_assert(NREG == 0 || (P::ELEM == 1 && L2N - VTOP - NREG >= 11), "register stages: int8, >= 2^11 LLRs");
+  static_assert(VTOP == 0 || (P::ELEM == 1 && NREG >= 1), "a virtual top stage feeds a register stage");
   uint32_t rs[R::total()];
 
   // highest alpha stage in LDS: scratch for leaves at register stages
-  static constexpr int kTopLds = L2N - NREG - 1;
+  static constexpr int kTopLds = L2N - 1 - VTOP - NREG;
 
   // Gives the registers of stage S new names before an op reads them, so
   // that no unpacked copies made by an earlier op on the same values stay
@@ -1128,6 +1135,91 @@ struct DecU : Dec<P> {
         }
       }
     }
+  }
+
+  // ------------------------------------------- fused root-child ops
+  // The node of stage L2N-1 at offset O (0 or 2^(L2N-1)) runs XC (f, g or
+  // g_0R, eq. (1)/(2)) on its LLRs, which are the root's op YC applied to
+  // the channel: alpha_v[i] = YC(c[i], c[i + 2^(L2N-1)]) with the root's
+  // left-child bits (g).  Output: the register stage L2N-2.  Same integer
+  // operations in the same order as the two separate ops.
+  template <uint32_t XC, uint32_t YC, int O>
+  __device__ __forceinline__ void fused_top() {
+    constexpr int H1 = 1 << (L2N - 1), H2 = 1 << (L2N - 2);
+    constexpr int IT = H2 / 1024;
+    constexpr int U = 2;
+    static_assert(VTOP == 1 && R::has(L2N - 2), "fused root-child op needs the virtual top stage");
+    const int lane = this->lane;
+#pragma unroll
+    for (int b0 = 0; b0 < IT; b0 += U) {
+      u32x4 c00[U], c01[U], c10[U], c11[U];
+      uint32_t by0[U], by1[U], bx[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int it = b0 + u;
+        const int i0 = it * 1024 + lane * 16;
+        c00[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(this->chr, lane * 16, it * 1024, 0));
+        c01[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(this->chr, lane * 16, it * 1024 + H1, 0));
+        c10[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(this->chr, lane * 16, it * 1024 + H2, 0));
+        c11[u] =
+            __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(this->chr, lane * 16, it * 1024 + H2 + H1, 0));
+        by0[u] = by1[u] = bx[u] = 0;
+        if constexpr (YC == DOP_G) {  // bits of the root's left child, at i and i + H2
+          by0[u] = this->beta[i0 >> 5] >> (i0 & 31);
+          by1[u] = this->beta[(i0 + H2) >> 5] >> ((i0 + H2) & 31);
+        }
+        if constexpr (XC == DOP_G) bx[u] = this->beta[(O + i0) >> 5] >> ((O + i0) & 31);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int it = b0 + u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const s2 a0l = chanx(unpack_lo(c00[u][k])), a0h = chanx(unpack_hi(c00[u][k]));
+          const s2 a1l = chanx(unpack_lo(c01[u][k])), a1h = chanx(unpack_hi(c01[u][k]));
+          const s2 b0l = chanx(unpack_lo(c10[u][k])), b0h = chanx(unpack_hi(c10[u][k]));
+          const s2 b1l = chanx(unpack_lo(c11[u][k])), b1h = chanx(unpack_hi(c11[u][k]));
+          s2 xl, xh, yl, yh;
+          if constexpr (YC == DOP_F) {
+            xl = fx(a0l, a1l);
+            xh = fx(a0h, a1h);
+            yl = fx(b0l, b1l);
+            yh = fx(b0h, b1h);
+          } else if constexpr (YC == DOP_G) {
+            const u32x2 sx = *(const LDS u32x2*)(this->lut + 2 * ((by0[u] >> (4 * k)) & 15u));
+            const u32x2 sy = *(const LDS u32x2*)(this->lut + 2 * ((by1[u] >> (4 * k)) & 15u));
+            xl = gx(a0l, a1l, as_s2(sx[0]));
+            xh = gx(a0h, a1h, as_s2(sx[1]));
+            yl = gx(b0l, b1l, as_s2(sy[0]));
+            yh = gx(b0h, b1h, as_s2(sy[1]));
+          } else {
+            xl = g0x(a0l, a1l);
+            xh = g0x(a0h, a1h);
+            yl = g0x(b0l, b1l);
+            yh = g0x(b0h, b1h);
+          }
+          s2 rl, rh;
+          if constexpr (XC == DOP_F) {
+            rl = fx(xl, yl);
+            rh = fx(xh, yh);
+          } else if constexpr (XC == DOP_G) {
+            const u32x2 sg = *(const LDS u32x2*)(this->lut + 2 * ((bx[u] >> (4 * k)) & 15u));
+            rl = gx(xl, yl, as_s2(sg[0]));
+            rh = gx(xh, yh, as_s2(sg[1]));
+          } else {
+            rl = g0x(xl, yl);
+            rh = g0x(xh, yh);
+          }
+          rs[R::base(L2N - 2) + 4 * it + k] = pack4(rl, rh);
+        }
+      }
+    }
+  }
+
+  template <uint32_t W, uint32_t YC>
+  __device__ __forceinline__ void step_fused() {
+    fused_top<W & 0xffu, YC, (int)(W >> 16)>();
+    wave_sync();
   }
 
   // ------------------------------------------------ wide F / G (float)

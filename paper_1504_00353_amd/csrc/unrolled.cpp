@@ -95,46 +95,101 @@ bool write_file_atomic(const std::string& path, const std::vector<char>& data) {
 
 }  // namespace
 
-int unrolled_nreg(int log2n, int llr_type) {
-  if (llr_type != 0) return 0;
-  if (log2n == 15) return 2;
-  if (log2n == 14) return 1;
-  return 0;
+UnrolledLayout unrolled_layout(const Plan& p, int llr_type) {
+  UnrolledLayout L;
+  if (llr_type != 0) return L;
+  if (p.log2n == 15) {
+    L.nreg = 2;
+    // the virtual top stage needs both children of the root to be inner
+    // nodes (or Rate-0): no decision node of size N/2
+    bool ok = true;
+    for (int i = 0; i < p.nops; ++i) {
+      const unsigned code = p.dops[i] & 0xffu, st = (p.dops[i] >> 8) & 0xffu;
+      if ((st == 15 || st == 14) && code >= DOP_R1 && code <= DOP_SPC) ok = false;
+    }
+    L.vtop = ok ? 1 : 0;
+  } else if (p.log2n == 14) {
+    L.nreg = 1;
+  }
+  return L;
 }
 
-std::string unrolled_source(const Plan& p, int llr_type) {
-  const int nreg = unrolled_nreg(p.log2n, llr_type);
+int unrolled_wave_bytes(const Plan& p, int llr_type) {
+  const UnrolledLayout L = unrolled_layout(p, llr_type);
+  return wave_lds_bytes(p.log2n, llr_type == 1 ? 4 : 1, L.nreg + L.vtop);
+}
+
+namespace {
+
+// Waves per SIMD the LDS slot allows (160 KB per CU, 4 SIMDs), 1..4: the
+// register budget the generated kernel is compiled for.
+int waves_per_simd_for(int wave_bytes) {
+  int w = (160 * 1024 / wave_bytes) / 4;
+  return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
+// The decoder object and its initialisation for one code.
+std::string decoder_decl(const Plan& p, int llr_type, const char* frame_expr, const char* trace_expr) {
+  const UnrolledLayout L = unrolled_layout(p, llr_type);
   const char* pol = llr_type == 1 ? "PF32" : "PI8";
+  std::string s;
+  s += "  polar::DecU<polar::" + std::string(pol) + ", " + std::to_string(p.log2n) + ", " + std::to_string(L.nreg) +
+       ", " + std::to_string(L.vtop) + "> d;\n";
+  s += "  d.init(base, lane, " + std::to_string(p.log2n) + ", " + std::to_string(p.k) + ", llr, " + frame_expr +
+       ", bits, " + trace_expr + ", " + std::to_string(L.nreg + L.vtop) + ");\n";
+  return s;
+}
+
+// The op calls of one code.  With the virtual top stage the root's f / g /
+// g_0R emit nothing and the ops of its children become fused ops.
+void append_ops(std::string& s, const Plan& p, int llr_type) {
+  const UnrolledLayout L = unrolled_layout(p, llr_type);
+  char line[96];
+  unsigned root_op = DOP_F;
+  for (int i = 0; i < p.nops; ++i) {
+    const unsigned w = p.dops[i];
+    const unsigned code = w & 0xffu;
+    const int st = (int)((w >> 8) & 0xffu);
+    if (L.vtop && st == p.log2n && code <= DOP_G0R) {
+      root_op = code;
+      continue;
+    }
+    if (L.vtop && st == p.log2n - 1 && code <= DOP_G0R)
+      snprintf(line, sizeof line, "  d.template step_fused<0x%08xu, %uu>();\n", w, root_op);
+    else
+      snprintf(line, sizeof line, "  d.template step_c<0x%08xu>();\n", w);
+    s += line;
+  }
+}
+
+}  // namespace
+
+std::string unrolled_source(const Plan& p, int llr_type) {
   const char* chan = llr_type == 1 ? "float" : "int8_t";
+  const int wps = waves_per_simd_for(unrolled_wave_bytes(p, llr_type));
   std::string s;
   s.reserve(64 * (size_t)p.nops + 4096);
   s += "// generated: unrolled decoder for one polar code\n";
   s += "// N=" + std::to_string(p.n) + " K=" + std::to_string(p.k) + " algo=" + std::to_string(p.algo) +
        " llr=" + std::to_string(llr_type) + " ops=" + std::to_string(p.nops) + "\n";
   s += "#include \"decode_ops.h\"\n\nnamespace {\n\n";
-  s += "template <class D>\n__device__ __forceinline__ void run(D& d) {\n";
-  char line[80];
-  for (int i = 0; i < p.nops; ++i) {
-    snprintf(line, sizeof line, "  d.template step_c<0x%08xu>();\n", p.dops[i]);
-    s += line;
-  }
-  s += "}\n\n";
   s += "__device__ __forceinline__ void entry(const " + std::string(chan) + "* llr, int nframes, uint8_t* bits, " +
        chan + "* trace, int wave_bytes, unsigned char* smem) {\n";
   s += "  const int lane = threadIdx.x & 63;\n";
   s += "  const int wid = (int)polar::rfl(threadIdx.x >> 6);\n";
   s += "  const int frame = blockIdx.x * (blockDim.x >> 6) + wid;\n";
   s += "  if (frame >= nframes) return;\n";
-  s += "  polar::DecU<polar::" + std::string(pol) + ", " + std::to_string(p.log2n) + ", " + std::to_string(nreg) +
-       "> d;\n";
-  s += "  d.init((LDS unsigned char*)smem + wid * wave_bytes, lane, " + std::to_string(p.log2n) + ", " +
-       std::to_string(p.k) + ", llr, frame, bits, trace, " + std::to_string(nreg) + ");\n";
-  s += "  run(d);\n  d.finish();\n}\n\n}  // namespace\n\n";
-  s += "extern \"C\" __global__ void __launch_bounds__(256) polar_unrolled(const " + std::string(chan) +
+  s += "  LDS unsigned char* base = (LDS unsigned char*)smem + wid * wave_bytes;\n";
+  s += decoder_decl(p, llr_type, "frame", "trace");
+  append_ops(s, p, llr_type);
+  s += "  d.finish();\n}\n\n}  // namespace\n\n";
+  const std::string attrs =
+      "__launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(" + std::to_string(wps) + "))) ";
+  s += "extern \"C\" __global__ void " + attrs + "polar_unrolled(const " + std::string(chan) +
        "* __restrict__ llr, int nframes, uint8_t* __restrict__ bits, int wave_bytes) {\n";
   s += "  extern __shared__ __align__(16) unsigned char smem[];\n";
   s += "  entry(llr, nframes, bits, nullptr, wave_bytes, smem);\n}\n\n";
-  s += "extern \"C\" __global__ void __launch_bounds__(256) polar_unrolled_trace(const " + std::string(chan) +
+  s += "extern \"C\" __global__ void " + attrs + "polar_unrolled_trace(const " + std::string(chan) +
        "* __restrict__ llr, int nframes, uint8_t* __restrict__ bits, " + chan +
        "* __restrict__ trace, int wave_bytes) {\n";
   s += "  extern __shared__ __align__(16) unsigned char smem[];\n";
@@ -143,7 +198,6 @@ std::string unrolled_source(const Plan& p, int llr_type) {
 }
 
 std::string batch_source(const std::vector<const Plan*>& plans, int llr_type, int waves_per_simd) {
-  const char* pol = llr_type == 1 ? "PF32" : "PI8";
   const char* chan = llr_type == 1 ? "float" : "int8_t";
   std::string s;
   size_t total_ops = 0;
@@ -151,22 +205,14 @@ std::string batch_source(const std::vector<const Plan*>& plans, int llr_type, in
   s.reserve(64 * total_ops + 4096 * plans.size() + 4096);
   s += "// generated: persistent batch decoder for " + std::to_string(plans.size()) + " polar codes\n";
   s += "#include \"decode_ops.h\"\n\nnamespace {\n\n";
-  char line[96];
   for (size_t c = 0; c < plans.size(); ++c) {
     const Plan& p = *plans[c];
-    const int nreg = unrolled_nreg(p.log2n, llr_type);
     s += "// code " + std::to_string(c) + ": N=" + std::to_string(p.n) + " K=" + std::to_string(p.k) +
          " algo=" + std::to_string(p.algo) + "\n";
     s += "__device__ __noinline__ void dec_" + std::to_string(c) + "(LDS unsigned char* base, int lane, const " +
          chan + "* llr, uint8_t* bits) {\n";
-    s += "  polar::DecU<polar::" + std::string(pol) + ", " + std::to_string(p.log2n) + ", " + std::to_string(nreg) +
-         "> d;\n";
-    s += "  d.init(base, lane, " + std::to_string(p.log2n) + ", " + std::to_string(p.k) + ", llr, 0, bits, nullptr, " +
-         std::to_string(nreg) + ");\n";
-    for (int i = 0; i < p.nops; ++i) {
-      snprintf(line, sizeof line, "  d.template step_c<0x%08xu>();\n", p.dops[i]);
-      s += line;
-    }
+    s += decoder_decl(p, llr_type, "0", "nullptr");
+    append_ops(s, p, llr_type);
     s += "  d.finish();\n}\n\n";
   }
   s += "}  // namespace\n\n";
@@ -278,9 +324,9 @@ void unrolled_unload(UnrolledKernel& k) {
   k = UnrolledKernel();
 }
 
-int unrolled_launch(const UnrolledKernel& k, int log2n, int llr_type, const void* llr, int nframes, uint8_t* bits,
-                    void* trace, int waves_per_block, void* stream) {
-  int wb = wave_lds_bytes(log2n, llr_type == 1 ? 4 : 1, unrolled_nreg(log2n, llr_type));
+int unrolled_launch(const UnrolledKernel& k, const void* llr, int nframes, uint8_t* bits, void* trace,
+                    int waves_per_block, void* stream) {
+  int wb = k.wave_bytes;
   const unsigned grid = (unsigned)((nframes + waves_per_block - 1) / waves_per_block);
   const unsigned block = 64u * (unsigned)waves_per_block;
   const unsigned lds = (unsigned)wb * (unsigned)waves_per_block;

@@ -14,11 +14,18 @@ struct UnrolledKernel {
   hipModule_t module = nullptr;
   hipFunction_t fn = nullptr;
   hipFunction_t fn_trace = nullptr;
+  int wave_bytes = 0;  // LDS slot of one wavefront
 };
 
-// Top alpha stages a generated kernel keeps in registers for this length
-// and LLR type (int8 codes of N >= 16384).
-int unrolled_nreg(int log2n, int llr_type);
+// How a generated int8 kernel places the widest alpha stages: nreg stages
+// in registers, and with vtop the stage below the root not stored at all.
+struct UnrolledLayout {
+  int nreg = 0;
+  int vtop = 0;
+};
+UnrolledLayout unrolled_layout(const Plan& p, int llr_type);
+// LDS bytes of one wavefront of the generated kernel of this plan.
+int unrolled_wave_bytes(const Plan& p, int llr_type);
 
 // HIP source of the two kernels (plain and tracing) for the plan's device
 // schedule and the LLR type (0 int8, 1 float).
@@ -43,7 +50,7 @@ int unrolled_load(const std::vector<char>& code, UnrolledKernel& k);
 void unrolled_unload(UnrolledKernel& k);
 
 // Launches the loaded kernel; returns the hipError_t of the launch.
-int unrolled_launch(const UnrolledKernel& k, int log2n, int llr_type, const void* llr, int nframes, uint8_t* bits,
-                    void* trace, int waves_per_block, void* stream);
+int unrolled_launch(const UnrolledKernel& k, const void* llr, int nframes, uint8_t* bits, void* trace,
+                    int waves_per_block, void* stream);
 
 }  // namespace polar

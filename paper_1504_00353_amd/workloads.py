@@ -85,13 +85,17 @@ def _blocks(n, spec):
 
 
 # Frozen sets with every leaf kind at the widest node sizes of N = 32768 and
-# 16384 (the stages a generated int8 kernel keeps in registers).
+# 16384 (the stages a generated int8 kernel keeps in registers), and inner
+# root children reached through f, g and g_0R (its fused root-child ops).
 UNROLLED_MASKS = {
     "m32k_spc13_rep13_spc14": (32768, _blocks(32768, [("SPC", 8192), ("REP", 8192), ("SPC", 16384)])),
     "m32k_r013_r113_rep14": (32768, _blocks(32768, [("R0", 8192), ("R1", 8192), ("REP", 16384)])),
     "m32k_r114_r014": (32768, _blocks(32768, [("R1", 16384), ("R0", 16384)])),
     "m32k_rep12_spc12_r113_spc14": (32768, _blocks(32768, [("REP", 4096), ("SPC", 4096), ("R1", 8192),
                                                            ("SPC", 16384)])),
+    "m32k_r014_spc13_rep13": (32768, _blocks(32768, [("R0", 16384), ("SPC", 8192), ("REP", 8192)])),
+    "m32k_spc13_rep13_r013_r113": (32768, _blocks(32768, [("SPC", 8192), ("REP", 8192), ("R0", 8192),
+                                                            ("R1", 8192)])),
     "m16k_spc13_rep13": (16384, _blocks(16384, [("SPC", 8192), ("REP", 8192)])),
     "m16k_r113_spc13": (16384, _blocks(16384, [("R1", 8192), ("SPC", 8192)])),
 }
