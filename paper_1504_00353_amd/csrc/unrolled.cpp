@@ -140,11 +140,50 @@ std::string decoder_decl(const Plan& p, int llr_type, const char* frame_expr, co
   return s;
 }
 
+// Rough vector-instruction cost of one op (int8 kernels; a fit of the
+// generated code's instruction counts), used only to place the priority
+// steps below.
+double op_cost(unsigned code, int st, bool fused) {
+  const double size = (double)(1u << st);
+  if (fused) return (code == DOP_F ? 0.087 : 0.093) * 2.0 * size;
+  if (st <= kRegStages) {
+    static const double small[] = {5.0, 1.5, 3.7, 0.6, 1.4, 1.0, 2.0, 2.0, 20.0, 1.4, 0.0};
+    return code <= DOP_END ? small[code] : 0.0;
+  }
+  switch (code) {
+    case DOP_F: return 2.0 + 0.025 * size;
+    case DOP_G: case DOP_G0R: return 2.0 + 0.032 * size;
+    case DOP_R1: return 55.0 + 0.035 * size;
+    case DOP_REP: return 20.0 + 0.08 * size;
+    case DOP_SPC: return 80.0 + 0.15 * size;
+    default: return 2.0 + 0.0006 * size;
+  }
+}
+
 // The op calls of one code.  With the virtual top stage the root's f / g /
 // g_0R emit nothing and the ops of its children become fused ops.
+//
+// Progress priority: the decoder starts at wave priority 3 and steps down to
+// 2, 1 and 0 after 30%, 60% and 85% of its estimated work.  The waves that
+// share a SIMD then keep pace with each other (a wave that runs ahead yields
+// issue slots to the ones behind) instead of the oldest finishing first and
+// the last running alone, with too few waves to hide its latencies.
 void append_ops(std::string& s, const Plan& p, int llr_type) {
   const UnrolledLayout L = unrolled_layout(p, llr_type);
+  std::vector<double> cost((size_t)p.nops, 0.0);
+  double total = 0.0;
+  for (int i = 0; i < p.nops; ++i) {
+    const unsigned code = p.dops[i] & 0xffu;
+    const int st = (int)((p.dops[i] >> 8) & 0xffu);
+    if (L.vtop && st == p.log2n && code <= DOP_G0R) continue;
+    cost[(size_t)i] = op_cost(code, st, L.vtop && st == p.log2n - 1 && code <= DOP_G0R);
+    total += cost[(size_t)i];
+  }
+  static const double kSteps[3] = {0.30, 0.60, 0.85};
+  int next = 0;
+  double done = 0.0;
   char line[96];
+  s += "  __builtin_amdgcn_s_setprio(3);\n";
   unsigned root_op = DOP_F;
   for (int i = 0; i < p.nops; ++i) {
     const unsigned w = p.dops[i];
@@ -159,6 +198,12 @@ void append_ops(std::string& s, const Plan& p, int llr_type) {
     else
       snprintf(line, sizeof line, "  d.template step_c<0x%08xu>();\n", w);
     s += line;
+    done += cost[(size_t)i];
+    while (next < 3 && done >= kSteps[next] * total) {
+      snprintf(line, sizeof line, "  __builtin_amdgcn_s_setprio(%d);\n", 2 - next);
+      s += line;
+      ++next;
+    }
   }
 }
 
