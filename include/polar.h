@@ -93,6 +93,17 @@ polar_code* polar_construct_mask(int n, const uint8_t* frozen);
  * called before polar_prepare(); POLAR_ESTATE afterwards. */
 polar_status polar_configure(polar_code* code, int algo, int llr_type);
 
+/* Fast-SSC only: enable (1, the default) or disable (0) the fused nodes of
+ * the Fast-SSC function library (Sec. II-E): every internal node of size
+ * <= 64 whose children are a Rate-0 or repetition node (left) and a Rate-1
+ * or SPC node (right) -- the P_01, 0SPC and RepSPC functions, and the
+ * repetition / Rate-1 pair -- runs as one device op instead of five (or
+ * three).  The decoded bits and the trace are identical either way; the
+ * switch exists to measure the effect.  Ignored by plain SC.  Must be
+ * called before polar_prepare(); POLAR_ESTATE afterwards, POLAR_EINVAL for
+ * another value. */
+polar_status polar_set_fused_nodes(polar_code* code, int enable);
+
 /* Selects the kernel (polar_kernel); default POLAR_KERNEL_SCHEDULE.  Must
  * be called before polar_prepare(); POLAR_ESTATE afterwards. */
 polar_status polar_set_kernel(polar_code* code, int kernel);
@@ -135,6 +146,27 @@ polar_status polar_frozen_mask(const polar_code* code, uint8_t* out);
  * most cap entries to each non-NULL array and sets *n_ops to the total. */
 polar_status polar_schedule(const polar_code* code, int32_t* kinds, int32_t* sizes,
                             int32_t* offsets, int cap, int* n_ops);
+
+/* Device ops: what the kernels actually run (polar_device_schedule).  One
+ * 32-bit word per op: op | stage << 8 | node offset << 16, where stage is
+ * log2 of the node size.  F / G / G_0R read the node at that stage and write
+ * its child; leaves, combines and fused nodes act on the node itself. */
+typedef enum {
+  POLAR_DOP_F = 0, POLAR_DOP_G = 1, POLAR_DOP_G_0R = 2,
+  POLAR_DOP_COMBINE = 3, POLAR_DOP_COMBINE_0R = 4,
+  POLAR_DOP_COMBINE_R0 = 5,  /* right child Rate-0: clear its estimate */
+  POLAR_DOP_INFO = 6, POLAR_DOP_REP = 7, POLAR_DOP_SPC = 8,
+  POLAR_DOP_FLUSH = 9,       /* a finished size-64 estimate to LDS */
+  POLAR_DOP_P01 = 11,        /* fused: left Rate-0, right Rate-1 */
+  POLAR_DOP_0SPC = 12,       /* fused: left Rate-0, right SPC */
+  POLAR_DOP_REPSPC = 13,     /* fused: left repetition, right SPC */
+  POLAR_DOP_REPR1 = 14       /* fused: left repetition, right Rate-1 */
+} polar_dev_op;
+
+/* The device schedule (polar_dev_op words, in execution order) of the code
+ * as configured.  Writes at most cap words to ops (may be NULL) and sets
+ * *n_ops to the total.  Host only. */
+polar_status polar_device_schedule(const polar_code* code, uint32_t* ops, int cap, int* n_ops);
 
 /* Host encoder: x = u G_N (Sec. II-A) with u_A taken from info (packed
  * rows of ceil(K/8) bytes, information bits in increasing index order) and

@@ -16,10 +16,14 @@ ALGO = {"fastssc": 0, "sc": 1}
 LLR = {"i8": 0, "f32": 1}
 KERNEL = {"schedule": 0, "unrolled": 1}
 OP_NAMES = ["F", "G", "G_0R", "Combine", "Combine_0R", "Info", "Repetition", "SPC"]
+DEV_OP_NAMES = ["F", "G", "G_0R", "Combine", "Combine_0R", "Combine_R0", "Info", "Repetition", "SPC", "Flush",
+                "End", "P_01", "0SPC", "RepSPC", "Rep-R1"]
 EXPORTS = [
     "polar_construct", "polar_construct_mask", "polar_configure", "polar_prepare", "polar_destroy",
     "polar_last_status", "polar_strerror", "polar_n", "polar_k", "polar_frozen_mask", "polar_schedule",
-    "polar_encode", "polar_decode", "polar_decode_trace", "polar_set_kernel", "polar_build_kernel",
+    "polar_encode", "polar_decode", "polar_decode_trace", "polar_set_kernel", "polar_set_fused_nodes",
+    "polar_device_schedule",
+    "polar_build_kernel",
     "polar_last_message", "polar_batch_create", "polar_batch_build_kernel", "polar_batch_prepare",
     "polar_batch_set_frames", "polar_batch_decode", "polar_batch_decode_desc", "polar_batch_tune",
     "polar_batch_launch_shape", "polar_batch_destroy", "polar_server_create", "polar_server_submit",
@@ -53,6 +57,8 @@ def _lib():
         L.polar_configure.argtypes = [P, I, I]
         L.polar_prepare.argtypes = [P]
         L.polar_set_kernel.argtypes = [P, I]
+        L.polar_set_fused_nodes.argtypes = [P, I]
+        L.polar_device_schedule.argtypes = [P, P, I, P]
         L.polar_build_kernel.argtypes = [P]
         L.polar_destroy.argtypes = [P]
         L.polar_destroy.restype = None
@@ -114,7 +120,7 @@ class Code:
     """A polar code plus its decoder schedule (host) and device tables."""
 
     def __init__(self, n=None, k=None, design_db=None, algo="fastssc", llr="i8", frozen=None, prepare=True,
-                 kernel="schedule"):
+                 kernel="schedule", fused=True):
         L = _lib()
         if frozen is not None:
             frozen = np.ascontiguousarray(frozen, dtype=np.uint8)
@@ -130,6 +136,8 @@ class Code:
         _check(L.polar_configure(self._h, ALGO[algo], LLR[llr]), "polar_configure")
         self.kernel = kernel
         _check(L.polar_set_kernel(self._h, KERNEL[kernel]), "polar_set_kernel")
+        self.fused = bool(fused)
+        _check(L.polar_set_fused_nodes(self._h, 1 if fused else 0), "polar_set_fused_nodes")
         self.prepared = False
         if prepare:
             self.prepare()
@@ -165,6 +173,16 @@ class Code:
         out = np.zeros(self.n, np.uint8)
         _check(_lib().polar_frozen_mask(self._h, _np_ptr(out)), "polar_frozen_mask")
         return out
+
+    def device_schedule(self):
+        """The device op words the kernels run: (op, stage, offset) with op a
+        DEV_OP_NAMES entry."""
+        L = _lib()
+        cnt = ctypes.c_int(0)
+        _check(L.polar_device_schedule(self._h, None, 0, ctypes.byref(cnt)), "polar_device_schedule")
+        w = np.zeros(max(cnt.value, 1), np.uint32)
+        _check(L.polar_device_schedule(self._h, _np_ptr(w), cnt.value, ctypes.byref(cnt)), "polar_device_schedule")
+        return [(DEV_OP_NAMES[int(x) & 255], (int(x) >> 8) & 255, int(x) >> 16) for x in w[:cnt.value]]
 
     def schedule(self):
         cnt = ctypes.c_int(0)

@@ -120,6 +120,19 @@ polar_status polar_configure(polar_code* c, int algo, int llr_type) {
   return set(POLAR_OK);
 }
 
+polar_status polar_set_fused_nodes(polar_code* c, int enable) {
+  if (!c) return set(POLAR_EINVAL);
+  if (c->prepared) return set(POLAR_ESTATE);
+  if (enable != 0 && enable != 1) return set(POLAR_EINVAL);
+  try {
+    c->plan.fuse = enable;
+    polar::build_schedule(c->plan);
+  } catch (const std::bad_alloc&) {
+    return set(POLAR_ENOMEM);
+  }
+  return set(POLAR_OK);
+}
+
 polar_status polar_set_kernel(polar_code* c, int kernel) {
   if (!c) return set(POLAR_EINVAL);
   if (c->prepared) return set(POLAR_ESTATE);
@@ -231,6 +244,20 @@ polar_status polar_schedule(const polar_code* c, int32_t* kinds, int32_t* sizes,
     if (sizes) sizes[i] = c->plan.lsize[i];
     if (offsets) offsets[i] = c->plan.loff[i];
   }
+  if (n_ops) *n_ops = total;
+  return set(POLAR_OK);
+}
+
+static_assert(POLAR_DOP_F == polar::DOP_F && POLAR_DOP_G_0R == polar::DOP_G0R &&
+                  POLAR_DOP_COMBINE_R0 == polar::DOP_CR0 && POLAR_DOP_SPC == polar::DOP_SPC &&
+                  POLAR_DOP_FLUSH == polar::DOP_FLUSH && POLAR_DOP_P01 == polar::DOP_P01 &&
+                  POLAR_DOP_REPR1 == polar::DOP_REPR1,
+              "public device-op codes follow the kernels' codes");
+
+polar_status polar_device_schedule(const polar_code* c, uint32_t* ops, int cap, int* n_ops) {
+  if (!c || cap < 0) return set(POLAR_EINVAL);
+  const int total = c->plan.nops;
+  for (int i = 0; i < total && i < cap && ops; ++i) ops[i] = c->plan.dops[(size_t)i];
   if (n_ops) *n_ops = total;
   return set(POLAR_OK);
 }

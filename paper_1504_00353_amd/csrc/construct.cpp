@@ -113,6 +113,18 @@ struct Walker {
 
   void dev(DeviceOp op, int stage, int o) { p.dops.push_back(pack_op(op, stage, o)); }
 
+  // The fused op of an internal node at o whose children (size h) are a
+  // Rate-0 or repetition node on the left and a Rate-1 or SPC node on the
+  // right, else -1.
+  int pair_op(int o, int h) const {
+    const NodeKind l = device_kind(o, h), r = device_kind(o + h, h);
+    if (l == N_RATE0 && r == N_RATE1) return DOP_P01;
+    if (l == N_RATE0 && r == N_SPC) return DOP_0SPC;
+    if (l == N_REP && r == N_SPC) return DOP_REPSPC;
+    if (l == N_REP && r == N_RATE1) return DOP_REPR1;
+    return -1;
+  }
+
   // needed: some later G or combine reads this node's beta (the estimate of
   // the root and of the nodes on its right spine is never read).
   void device(int o, int stage, bool needed) {
@@ -127,7 +139,10 @@ struct Walker {
         const int h = size / 2;
         const bool left_rate0 = frozen_count(o, h) == h;
         const bool right_rate0 = frozen_count(o + h, h) == h;
-        if (left_rate0) {
+        const int pair = p.algo == 0 && p.fuse && stage <= kRegStages ? pair_op(o, h) : -1;
+        if (pair >= 0) {
+          dev((DeviceOp)pair, stage, o);
+        } else if (left_rate0) {
           dev(DOP_G0R, stage, o);
           device(o + h, stage - 1, needed);
           if (needed) dev(DOP_C0R, stage, o);

@@ -320,6 +320,69 @@ struct Dec {
     }
   }
 
+  // Fused leaf-pair node of size NV = 2^S (DOP_P01 .. DOP_REPR1): the left
+  // child (size H = NV/2) is Rate-0 or a repetition node, the right child
+  // Rate-1 or SPC.  Same arithmetic as f, the repetition sum, g, the
+  // right leaf and the combine run as separate ops; the node's beta goes to
+  // the window and its information bits (left leaf first) to the output in
+  // one step each.
+  template <int S>
+  __device__ __forceinline__ void small_pair(uint32_t code, int o) {
+    constexpr int NV = 1 << S, H = NV >> 1;
+    const int off = o & 63;
+    const uint64_t m = low_mask(H);
+    const bool rep_left = code == DOP_REPSPC || code == DOP_REPR1;
+    const bool spc_right = code == DOP_REPSPC || code == DOP_0SPC;
+    const float x = a[S];
+    const float y = from_up<H>(x);
+    bool rep = false;
+    float g;
+    if (rep_left) {
+      const float f = fmin_sum(x, y);
+      if (tr && lane < H) tr[o + lane] = P::to_chan(f);
+      float s = f;
+      if constexpr (H >= 32) s += from_up<16>(s);
+      if constexpr (H >= 16) s += from_up<8>(s);
+      if constexpr (H >= 8) s += from_up<4>(s);
+      if constexpr (H >= 4) s += from_up<2>(s);
+      if constexpr (H >= 2) s += from_up<1>(s);
+      rep = rflf(s) < 0.0f;
+      g = P::clamp32(y + (rep ? -x : x));
+    } else {
+      g = P::clamp32(y + x);
+    }
+    if (tr && lane < H) tr[o + H + lane] = P::to_chan(g);
+    uint64_t hd = ballot(g < 0.0f) & m;
+    uint64_t out;
+    int nout;
+    if (spc_right) {
+      if (__popcll(hd) & 1) {
+        float v = lane < H ? fabsf(g) : 3.0e38f;
+        if constexpr (H >= 32) v = fminf(v, from_up<16>(v));
+        if constexpr (H >= 16) v = fminf(v, from_up<8>(v));
+        if constexpr (H >= 8) v = fminf(v, from_up<4>(v));
+        if constexpr (H >= 4) v = fminf(v, from_up<2>(v));
+        if constexpr (H >= 2) v = fminf(v, from_up<1>(v));
+        const float mn = rflf(v);
+        const uint64_t cand = ballot(lane < H && fabsf(g) == mn);
+        hd ^= 1ull << (__ffsll((unsigned long long)cand) - 1);
+      }
+      out = transform64(hd, H) >> 1;
+      nout = H - 1;
+    } else {
+      out = transform64(hd, H);
+      nout = H;
+    }
+    set_win(off, low_mask(NV), (((rep ? m : 0ull) ^ hd) | (hd << H)));
+    if (rep_left) {
+      pend_v = (rep ? 1ull : 0ull) | (out << 1);
+      pend_n = nout + 1;
+    } else {
+      pend_v = out;
+      pend_n = nout;
+    }
+  }
+
   __device__ __forceinline__ void small_combine(uint32_t code, int S, int o) {
     const int h = 1 << (S - 1);
     const int off = o & 63;
@@ -869,6 +932,14 @@ struct Dec {
       small_combine(code, S, o);
     } else if (code == DOP_FLUSH) {
       flush(o);
+    } else if (is_pair_op(code)) {
+      switch (S) {
+        case 2: small_pair<2>(code, o); break;
+        case 3: small_pair<3>(code, o); break;
+        case 4: small_pair<4>(code, o); break;
+        case 5: small_pair<5>(code, o); break;
+        default: small_pair<6>(code, o); break;
+      }
     } else {
       switch (S) {
         case 0: small_leaf<0>(code, o); break;
@@ -1393,6 +1464,8 @@ struct DecU : Dec<P> {
         this->small_combine(code, S, o);
       else if constexpr (code == DOP_FLUSH)
         this->flush(o);
+      else if constexpr (is_pair_op(code))
+        this->template small_pair<S>(code, o);
       else
         this->template small_leaf<S>(code, o);
     } else if constexpr (code <= DOP_G0R) {
@@ -1411,7 +1484,7 @@ struct DecU : Dec<P> {
     } else {
       this->template leaf_r1spc<S>(code, o, S - 1 < kTopLds ? S - 1 : kTopLds);
     }
-    if constexpr (code >= DOP_R1 && code <= DOP_SPC) this->settle();
+    if constexpr ((code >= DOP_R1 && code <= DOP_SPC) || is_pair_op(code)) this->settle();
     wave_sync();
   }
 };

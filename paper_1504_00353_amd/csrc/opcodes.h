@@ -23,7 +23,17 @@ enum DeviceOp : unsigned {
   DOP_SPC = 8,    // single-parity-check leaf (Sec. II-E)
   DOP_FLUSH = 9,  // write the 64-bit beta window of a finished size-64 node to LDS
   DOP_END = 10,   // padding after the last op
+  // Fused nodes of size <= 64 whose two children are leaves (the P_01, 0SPC
+  // and RepSPC functions of the Fast-SSC library, Sec. II-E, and Rep-R1):
+  // the whole subtree f / leaf / g / leaf / combine in one op, with the
+  // arithmetic of the separate ops.
+  DOP_P01 = 11,     // left Rate-0, right Rate-1
+  DOP_0SPC = 12,    // left Rate-0, right SPC
+  DOP_REPSPC = 13,  // left repetition, right SPC
+  DOP_REPR1 = 14,   // left repetition, right Rate-1
 };
+
+constexpr bool is_pair_op(unsigned code) { return code >= DOP_P01 && code <= DOP_REPR1; }
 
 constexpr int kRegStages = 6;  // stages 0..6 (sizes 1..64) are register resident
 constexpr int kMaxLog2N = 15;  // N <= 32768

@@ -147,8 +147,8 @@ double op_cost(unsigned code, int st, bool fused) {
   const double size = (double)(1u << st);
   if (fused) return (code == DOP_F ? 0.087 : 0.093) * 2.0 * size;
   if (st <= kRegStages) {
-    static const double small[] = {5.0, 1.5, 3.7, 0.6, 1.4, 1.0, 2.0, 2.0, 20.0, 1.4, 0.0};
-    return code <= DOP_END ? small[code] : 0.0;
+    static const double small[] = {5.0, 1.5, 3.7, 0.6, 1.4, 1.0, 2.0, 2.0, 20.0, 1.4, 0.0, 6.0, 24.0, 28.0, 10.0};
+    return code <= DOP_REPR1 ? small[code] : 0.0;
   }
   switch (code) {
     case DOP_F: return 2.0 + 0.025 * size;

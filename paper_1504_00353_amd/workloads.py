@@ -57,6 +57,15 @@ ALL = [SC_1024, FSSC_32K, FSSC_32K_F32, MIXED, SERVING, STRESS]
 
 # Further codes whose unrolled kernels are built ahead of time: the small
 # codes of the smoke run and of the unrolled-kernel parity tests.
+# unrolled kernels built with the fused leaf-pair nodes switched off (the
+# fused-vs-separate comparison)
+UNROLLED_UNFUSED = [
+    (1024, 512, 2.5, "fastssc", "i8"),
+    (1024, 512, 2.5, "fastssc", "f32"),
+    (4096, 3686, 4.0, "fastssc", "i8"),
+    (32768, 29492, 4.0, "fastssc", "i8"),
+]
+
 UNROLLED_EXTRA = [
     (1024, 512, 2.5, "fastssc", "i8"),
     (1024, 512, 2.5, "fastssc", "f32"),
@@ -87,7 +96,34 @@ def _blocks(n, spec):
 # Frozen sets with every leaf kind at the widest node sizes of N = 32768 and
 # 16384 (the stages a generated int8 kernel keeps in registers), and inner
 # root children reached through f, g and g_0R (its fused root-child ops).
+def pair_blocks():
+    """Every fused leaf-pair node (left Rate-0 or repetition, right Rate-1 or
+    SPC) at every child size 2..32 where the pair exists (P_01 from 2, the
+    others from 4), largest first so every block is aligned to its size."""
+    spec = []
+    for h in (32, 16, 8, 4, 2):
+        for left, right in (("R0", "R1"), ("R0", "SPC"), ("REP", "SPC"), ("REP", "R1")):
+            if h < 4 and (right == "SPC" or left == "REP"):
+                continue  # SPC leaves start at 4; repetition 2 + Rate-1 2 is itself an SPC node
+            spec += [(left, h), (right, h)]
+    return spec
+
+
+def _pairs_mask(n):
+    spec = pair_blocks()
+    used = sum(size for _, size in spec)
+    # the rest: aligned groups of a size-8 RepSPC and two size-4 P_01 pairs,
+    # then Rate-1 bits
+    rest = []
+    while used + 16 <= n:
+        rest += [("REP", 4), ("SPC", 4), ("R0", 2), ("R1", 2), ("R0", 2), ("R1", 2)]
+        used += 16
+    rest += [("R1", 1)] * (n - used)
+    return _blocks(n, spec + rest)
+
+
 UNROLLED_MASKS = {
+    "m2k_leaf_pairs": (2048, _pairs_mask(2048)),
     "m32k_spc13_rep13_spc14": (32768, _blocks(32768, [("SPC", 8192), ("REP", 8192), ("SPC", 16384)])),
     "m32k_r013_r113_rep14": (32768, _blocks(32768, [("R0", 8192), ("R1", 8192), ("REP", 16384)])),
     "m32k_r114_r014": (32768, _blocks(32768, [("R1", 16384), ("R0", 16384)])),

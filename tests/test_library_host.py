@@ -167,3 +167,76 @@ def test_batch_arguments_and_build(tmp_path, monkeypatch):
     assert len(os.listdir(tmp_path)) == 1
     assert L.polar_batch_decode(None, None, None, None) == binding.EINVAL
     L.polar_batch_destroy(None)
+
+
+def _leaf_kind(fr, o, size):
+    f = fr[o:o + size]
+    nf = int(f.sum())
+    if nf == size:
+        return "R0"
+    if nf == 0:
+        return "R1"
+    if size >= 2 and nf == size - 1 and not f[-1]:
+        return "REP"
+    if size >= 4 and nf == 1 and f[0]:
+        return "SPC"
+    return None
+
+
+def _expected_pairs(fr):
+    """(op, stage, offset) of every internal node of size <= 64 whose
+    children are Rate-0 / repetition (left) and Rate-1 / SPC (right), in
+    depth-first order."""
+    names = {("R0", "R1"): "P_01", ("R0", "SPC"): "0SPC", ("REP", "SPC"): "RepSPC", ("REP", "R1"): "Rep-R1"}
+    out = []
+
+    def walk(o, size):
+        if _leaf_kind(fr, o, size) is not None:
+            return
+        h = size // 2
+        key = (_leaf_kind(fr, o, h), _leaf_kind(fr, o + h, h))
+        if size <= 64 and key in names:
+            out.append((names[key], size.bit_length() - 1, o))
+            return
+        walk(o, h)
+        walk(o + h, h)
+    walk(0, len(fr))
+    return out
+
+
+def test_fused_leaf_pairs_in_device_schedule():
+    """The device schedule holds one fused op per leaf-pair node of size
+    <= 64 and none of the separate ops inside it; with the fusion off (or
+    for plain SC) it holds no fused op."""
+    from paper_1504_00353_amd import workloads
+    rng = np.random.default_rng(9)
+    masks = [np.asarray(workloads.UNROLLED_MASKS["m2k_leaf_pairs"][1], np.uint8), oracle.construct(32768, 29492, 4.0),
+             oracle.construct(1024, 512, 2.5)]
+    masks += [random_mask(n, rng, p) for n in (8, 64, 256, 1024) for p in (0.3, 0.5, 0.7)]
+    fused_names = ("P_01", "0SPC", "RepSPC", "Rep-R1")
+    for fr in masks:
+        on = binding.Code(frozen=fr, prepare=False).device_schedule()
+        off = binding.Code(frozen=fr, prepare=False, fused=False).device_schedule()
+        assert [t for t in on if t[0] in fused_names] == _expected_pairs(fr)
+        assert not [t for t in off if t[0] in fused_names]
+        sc = binding.Code(frozen=fr, algo="sc", prepare=False).device_schedule()
+        assert not [t for t in sc if t[0] in fused_names]
+        # a fused node replaces 5 (repetition left) or 3 (Rate-0 left) ops,
+        # 4 or 2 when its estimate is never read again (no combine)
+        saved = len(off) - len(on)
+        pairs = _expected_pairs(fr)
+        lo = sum(3 if name.startswith("Rep") else 1 for name, _, _ in pairs)
+        hi = sum(4 if name.startswith("Rep") else 2 for name, _, _ in pairs)
+        assert lo <= saved <= hi
+    pairs = _expected_pairs(np.asarray(workloads.UNROLLED_MASKS["m2k_leaf_pairs"][1], np.uint8))
+    for name in fused_names:
+        assert {st for nm, st, _ in pairs if nm == name} >= ({2, 3, 4, 5, 6} if name == "P_01" else {3, 4, 5, 6})
+
+
+def test_set_fused_nodes_arguments():
+    L = binding.lib()
+    c = binding.Code(64, 32, 2.5, prepare=False)
+    assert L.polar_set_fused_nodes(c.handle, 2) == binding.EINVAL
+    assert L.polar_set_fused_nodes(None, 1) == binding.EINVAL
+    assert L.polar_device_schedule(None, None, 0, None) == binding.EINVAL
+    assert L.polar_set_fused_nodes(c.handle, 0) == binding.OK

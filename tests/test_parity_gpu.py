@@ -191,7 +191,7 @@ def test_zero_frames_is_noop():
 
 def _unrolled_specs():
     from paper_1504_00353_amd import build
-    return [t for t in build._kernel_specs() if t[1] != "mask"]
+    return [t for t in build._kernel_specs() if t[1] != "mask" and len(t) == 5]
 
 
 @pytest.mark.parametrize("name", sorted(workloads.UNROLLED_MASKS))
@@ -240,3 +240,38 @@ def test_unrolled_ragged_frame_counts(frames):
     fr = code.frozen()
     _, _, l = make_frames(fr, 12, frames, 2.5, "i8")
     check_parity(code, fr, l, "fastssc", label="unrolled ragged %d" % frames)
+
+
+@pytest.mark.parametrize("spec", workloads.UNROLLED_UNFUSED, ids=lambda t: "%d_%d_%s" % (t[0], t[1], t[4]))
+@pytest.mark.parametrize("kernel", ["schedule", "unrolled"])
+def test_fused_nodes_identical_to_separate_ops(spec, kernel):
+    """The fused leaf-pair nodes (P_01, 0SPC, RepSPC, Rep-R1) compute what the
+    separate f / leaf / g / leaf / combine ops compute: bits and trace equal
+    with the fusion on and off, and equal to the oracle."""
+    n, k, d, algo, llr = spec
+    on = Code(n, k, d, algo=algo, llr=llr, kernel=kernel, fused=True)
+    off = Code(n, k, d, algo=algo, llr=llr, kernel=kernel, fused=False)
+    fr = on.frozen()
+    _, _, l = make_frames(fr, 21, 64 if n >= 16384 else 256, d, llr)
+    rng = np.random.default_rng(n + 5)
+    extra = [random_llrs(rng, 16, n, "f32" if llr == "f32" else "i8")]
+    if llr == "i8":
+        extra.append(random_llrs(rng, 16, n, "i8small"))
+    l = np.concatenate([l] + extra)
+    check_parity(on, fr, l, algo, label="fused %s %s" % (kernel, spec))
+    b1, t1 = gpu_decode(on, l, trace=True)
+    b0, t0 = gpu_decode(off, l, trace=True)
+    assert np.array_equal(b0, b1)
+    assert np.array_equal(t0.view(np.uint8), t1.view(np.uint8))
+
+
+@pytest.mark.parametrize("llr", ["i8", "i8small", "f32"])
+@pytest.mark.parametrize("fused", [True, False])
+def test_leaf_pair_mask_schedule_kernel(llr, fused):
+    """Every leaf-pair pattern at every child size (the fused ops' node
+    sizes 4..64), through the schedule kernel, fused and not."""
+    n, fr = workloads.UNROLLED_MASKS["m2k_leaf_pairs"]
+    fr = np.asarray(fr, np.uint8)
+    code = Code(frozen=fr, llr="f32" if llr == "f32" else "i8", fused=fused)
+    rng = np.random.default_rng(77 + len(llr))
+    check_parity(code, fr, random_llrs(rng, 200, n, llr), "fastssc", label="pairs %s %s" % (llr, fused))
