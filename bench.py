@@ -10,6 +10,10 @@ Gb/s single-core figure for this code.  Prints one JSON line:
   plain        the same frames decoded with one launch per frame;
   roofline     algorithmic HBM bytes (LLR in + info bits out) per launch
                over the decode kernel's mean duration vs 8 TB/s;
+  valu         the bound that actually holds: the kernel's vector-ALU
+               instructions per frame (committed counter summary) at one
+               wave64 instruction per 4 cycles on each of the 1,024 SIMDs at
+               2.4 GHz, as a time floor per launch vs the measured time;
   cpu_baseline the CPU oracle on a bounded sample on this host's cores;
   mixed_batch  the 65,536-frame mixed-code workload in one persistent,
                autotuned launch (information Gb/s, launch time, FER);
@@ -81,6 +85,37 @@ def measured_traffic(frames, kernel):
     except (KeyError, ValueError, ZeroDivisionError):
         return None
     return fetch + write
+
+
+VALU_CLOCK_GHZ = 2.4
+VALU_SIMDS = 1024  # 256 CUs x 4 SIMDs; a wave64 VALU instruction takes 4 cycles on a 16-lane SIMD
+
+
+def valu_view(frames, kernel, mean_kernel_ms):
+    """Vector-ALU floor of one launch from the committed counter summary
+    (SQ_INSTS_VALU per wave), or None when the summary is missing or was
+    taken on other kernel sources."""
+    if kernel != "unrolled":
+        return None
+    path = os.path.join(ROOT, "profiles", "polar_unrolled_i8_32768x29492_valu.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                a, b = line.split(":", 1)
+                kv[a.strip()] = b.strip().split()[0]
+    try:
+        if kv.get("kernel_source_hash") != kernel_source_hash():
+            return None
+        per_frame = float(kv["valu_insts_per_frame"])
+    except (KeyError, ValueError):
+        return None
+    floor_ms = frames * per_frame * 4.0 / VALU_SIMDS / (VALU_CLOCK_GHZ * 1e9) * 1e3
+    return {"bound": "alu", "valu_insts_per_frame": round(per_frame, 1), "clock_ghz": VALU_CLOCK_GHZ,
+            "floor_ms": round(floor_ms, 4), "frac": round(floor_ms / mean_kernel_ms, 4),
+            "what": "frames x VALU instructions x 4 cycles / 1024 SIMDs / clock, over the mean kernel time"}
 
 
 def copy_calibration(nbytes, reps):
@@ -385,6 +420,7 @@ def main():
                      "kernel": "polar_unrolled (int8)" if args.kernel == "unrolled" else "decode_kernel<int8>",
                      "bytes_per_frame": bytes_per_frame,
                      "mean_kernel_ms": round(mean_kernel_s * 1e3, 4)},
+        "valu": valu_view(frames, args.kernel, mean_kernel_s * 1e3),
     }
     if not args.no_mixed and args.kernel == "unrolled":
         result["mixed_batch"] = mixed_batch_bench(max(args.steps // 2, 3))

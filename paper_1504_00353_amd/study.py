@@ -100,6 +100,19 @@ def main():
                                                                      gbps, lat, len(code.schedule())))
                 code.close()
 
+    print("\n## Fused leaf-pair nodes (P_01, 0SPC, RepSPC, Rep-R1) on vs off, int8 Fast-SSC, %d frames\n" % args.frames)
+    print("| code | kernel | fused | device ops | info Gb/s | latency us |")
+    print("|---|---|---|---|---|---|")
+    for n, k, d in ((1024, 512, 2.5), (4096, 3686, 4.0), (32768, 29492, 4.0)):
+        for kernel in ("schedule", "unrolled"):
+            for fused in (False, True):
+                code = Code(n, k, d, llr="i8", kernel=kernel, fused=fused)
+                _, l = channel_frames(code, args.frames, d, "i8", gen)
+                gbps, lat = speed(code, l)
+                print("| (%d,%d) | %s | %s | %d | %.1f | %.1f |" % (n, k, kernel, "yes" if fused else "no",
+                                                                   len(code.device_schedule()), gbps, lat))
+                code.close()
+
     print("\n## Frame-error rate, Fast-SSC, int8 (6-bit) vs float32 LLRs, %d frames per point\n" % args.fer_frames)
     print("| code | Eb/N0 dB | FER int8 | FER float32 |")
     print("|---|---|---|---|")
