@@ -127,9 +127,15 @@ __device__ __forceinline__ uint32_t transform32(uint32_t x) {
 
 // ---------------------------------------------------------------------------
 // int8 LLRs as packed 16-bit integers scaled by 256 (the byte is the high
-// half of each 16-bit lane).  Sums are saturated by the packed add and then
-// clamped to +-127*256, which is exactly the 8-bit saturating g of
-// Listing 4 on the unscaled values.
+// half of each 16-bit lane); pack4 keeps the high bytes.
+//
+// Exact values are multiples of 256 in [-32512, 32512].  f and g return
+// "loose" values: exact, or 32767 standing for +127 (a saturated sum, or f
+// of two channel values -128).  Their high byte is the exact 8-bit result
+// (the saturating g of Listing 4; f with -128 read as -127), so a loose
+// value may be packed or fed to f as it is, and is clamped (tight) before
+// it feeds g.  The channel value -128 (-32768 here) may feed f directly:
+// f's saturating negation turns two of them into 32767.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ s2 as_s2(uint32_t x) { return __builtin_bit_cast(s2, x); }
 __device__ __forceinline__ uint32_t as_u(s2 x) { return __builtin_bit_cast(uint32_t, x); }
@@ -138,21 +144,28 @@ __device__ __forceinline__ s2 unpack_hi(uint32_t w) { return as_s2(__builtin_amd
 __device__ __forceinline__ uint32_t pack4(s2 lo, s2 hi) {
   return __builtin_amdgcn_perm(as_u(hi), as_u(lo), 0x07050301u);
 }
-__device__ __forceinline__ s2 sat127(s2 r) {
-  const s2 lo = {(short)-32512, (short)-32512}, hi = {(short)32512, (short)32512};
-  return __builtin_elementwise_min(__builtin_elementwise_max(r, lo), hi);
-}
-__device__ __forceinline__ s2 fx(s2 a, s2 b) {
-  return __builtin_elementwise_max(__builtin_elementwise_min(a, b), -__builtin_elementwise_max(a, b));
-}
-// s: +-1 per half (-1 where beta_l = 1)
-__device__ __forceinline__ s2 gx(s2 a, s2 b, s2 s) { return sat127(__builtin_elementwise_add_sat(b, a * s)); }
-__device__ __forceinline__ s2 g0x(s2 a, s2 b) { return sat127(__builtin_elementwise_add_sat(b, a)); }
-// channel value -128 is read as -127
-__device__ __forceinline__ s2 chanx(s2 a) {
+// lower clamp of a saturated sum: [-32768, 32767] -> [-32512, 32767]
+__device__ __forceinline__ s2 sat_lo(s2 r) {
   const s2 lo = {(short)-32512, (short)-32512};
-  return __builtin_elementwise_max(a, lo);
+  return __builtin_elementwise_max(r, lo);
 }
+// loose -> exact
+__device__ __forceinline__ s2 tight(s2 r) {
+  const s2 hi = {(short)32512, (short)32512};
+  return __builtin_elementwise_min(r, hi);
+}
+// f: sgn(a) sgn(b) min(|a|, |b|) = max(min(a, b), -max(a, b)); a, b loose or
+// channel values
+__device__ __forceinline__ s2 fx(s2 a, s2 b) {
+  const s2 z = {0, 0};
+  return __builtin_elementwise_max(__builtin_elementwise_min(a, b),
+                                   __builtin_elementwise_sub_sat(z, __builtin_elementwise_max(a, b)));
+}
+// g: b + s a, s = +-1 per half (-1 where beta_l = 1); a, b exact
+__device__ __forceinline__ s2 gx(s2 a, s2 b, s2 s) { return sat_lo(__builtin_elementwise_add_sat(b, a * s)); }
+__device__ __forceinline__ s2 g0x(s2 a, s2 b) { return sat_lo(__builtin_elementwise_add_sat(b, a)); }
+// channel value -128 read as -127 (exact), for the channel inputs of g
+__device__ __forceinline__ s2 chanx(s2 a) { return sat_lo(a); }
 
 // ---------------------------------------------------------------------------
 // Arithmetic policies
@@ -487,7 +500,7 @@ struct Dec {
         for (int k = 0; k < NW; ++k) {
           s2 al = unpack_lo(A[k]), ah = unpack_hi(A[k]);
           s2 bl = unpack_lo(B[k]), bh = unpack_hi(B[k]);
-          if constexpr (CH) {
+          if constexpr (CH && CODE != DOP_F) {
             al = chanx(al);
             ah = chanx(ah);
             bl = chanx(bl);
@@ -1084,7 +1097,7 @@ struct DecU : Dec<P> {
   template <uint32_t CODE, bool CH>
   __device__ __forceinline__ uint32_t fg_word(uint32_t A, uint32_t Bw, uint32_t b4) const {
     s2 al = unpack_lo(A), ah = unpack_hi(A), bl = unpack_lo(Bw), bh = unpack_hi(Bw);
-    if constexpr (CH) {
+    if constexpr (CH && CODE != DOP_F) {
       al = chanx(al);
       ah = chanx(ah);
       bl = chanx(bl);
@@ -1246,10 +1259,14 @@ struct DecU : Dec<P> {
         const int it = b0 + u;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const s2 a0l = chanx(unpack_lo(c00[u][k])), a0h = chanx(unpack_hi(c00[u][k]));
-          const s2 a1l = chanx(unpack_lo(c01[u][k])), a1h = chanx(unpack_hi(c01[u][k]));
-          const s2 b0l = chanx(unpack_lo(c10[u][k])), b0h = chanx(unpack_hi(c10[u][k]));
-          const s2 b1l = chanx(unpack_lo(c11[u][k])), b1h = chanx(unpack_hi(c11[u][k]));
+          s2 a0l = unpack_lo(c00[u][k]), a0h = unpack_hi(c00[u][k]);
+          s2 a1l = unpack_lo(c01[u][k]), a1h = unpack_hi(c01[u][k]);
+          s2 b0l = unpack_lo(c10[u][k]), b0h = unpack_hi(c10[u][k]);
+          s2 b1l = unpack_lo(c11[u][k]), b1h = unpack_hi(c11[u][k]);
+          if constexpr (YC != DOP_F) {  // channel values feeding g
+            a0l = chanx(a0l), a0h = chanx(a0h), a1l = chanx(a1l), a1h = chanx(a1h);
+            b0l = chanx(b0l), b0h = chanx(b0h), b1l = chanx(b1l), b1h = chanx(b1h);
+          }
           s2 xl, xh, yl, yh;
           if constexpr (YC == DOP_F) {
             xl = fx(a0l, a1l);
@@ -1268,6 +1285,9 @@ struct DecU : Dec<P> {
             xh = g0x(a0h, a1h);
             yl = g0x(b0l, b1l);
             yh = g0x(b0h, b1h);
+          }
+          if constexpr (XC != DOP_F) {  // loose values feeding g
+            xl = tight(xl), xh = tight(xh), yl = tight(yl), yh = tight(yh);
           }
           s2 rl, rh;
           if constexpr (XC == DOP_F) {

@@ -143,6 +143,44 @@ def test_stress_launch_262144_frames_sampled(n, k, kernel):
     assert (out.reshape(frames // pool, pool, -1) == expect[None]).all()
 
 
+@pytest.mark.parametrize("n,k", [(4096, 3686), (32768, 29492)])
+def test_stress_launch_graph_replays(n, k):
+    """The stress workload as a captured HIP graph of the unrolled decode
+    (262,144 frames per launch), replayed with eager work and
+    synchronisation in between: every replay equals the oracle on sampled
+    frames and tile by tile."""
+    code = Code(n, k, 4.0, llr="i8", kernel="unrolled")
+    fr = code.frozen()
+    pool = 2048
+    _, _, l = make_frames(fr, 6, pool, 4.5, "i8")
+    u, _, _ = oracle.decode(fr, l, "fastssc", nthreads=8)
+    expect = packed_info(fr, u)
+    frames = 262144
+    dev = torch.from_numpy(l).cuda().repeat(frames // pool, 1)
+    out = torch.zeros((frames, code.row_bytes), dtype=torch.uint8, device="cuda")
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        code.decode(dev, out=out, stream=s)  # eager launch before capture
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            code.decode(dev, out=out, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    rng = np.random.default_rng(1)
+    for rep in range(3):
+        out.fill_(0x5A)
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        idx = rng.choice(frames, size=2048, replace=False)
+        assert np.array_equal(o[idx], expect[idx % pool]), "replay %d" % rep
+        assert (o.reshape(frames // pool, pool, -1) == expect[None]).all(), "replay %d" % rep
+        del junk
+
+
 @pytest.mark.parametrize("n,k", [(64, 64), (4096, 4096), (64, 1), (32768, 1), (64, 63), (8192, 8191), (2, 1), (2, 2)])
 @pytest.mark.parametrize("kind", ["i8", "f32"])
 def test_degenerate_codes(n, k, kind):
