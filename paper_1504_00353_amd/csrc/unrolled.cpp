@@ -145,14 +145,14 @@ std::string decoder_decl(const Plan& p, int llr_type, const char* frame_expr, co
 // steps below.
 double op_cost(unsigned code, int st, bool fused) {
   const double size = (double)(1u << st);
-  if (fused) return (code == DOP_F ? 0.087 : 0.093) * 2.0 * size;
+  if (fused) return (code == DOP_F ? 0.075 : 0.085) * size;
   if (st <= kRegStages) {
     static const double small[] = {5.0, 1.5, 3.7, 0.6, 1.4, 1.0, 2.0, 2.0, 20.0, 1.4, 0.0, 6.0, 24.0, 28.0, 10.0};
     return code <= DOP_REPR1 ? small[code] : 0.0;
   }
   switch (code) {
     case DOP_F: return 2.0 + 0.025 * size;
-    case DOP_G: case DOP_G0R: return 2.0 + 0.032 * size;
+    case DOP_G: case DOP_G0R: return 2.0 + 0.028 * size;
     case DOP_R1: return 55.0 + 0.035 * size;
     case DOP_REP: return 20.0 + 0.08 * size;
     case DOP_SPC: return 80.0 + 0.15 * size;
@@ -164,7 +164,7 @@ double op_cost(unsigned code, int st, bool fused) {
 // g_0R emit nothing and the ops of its children become fused ops.
 //
 // Progress priority: the decoder starts at wave priority 3 and steps down to
-// 2, 1 and 0 after 30%, 60% and 85% of its estimated work.  The waves that
+// 2, 1 and 0 after 40%, 65% and 85% of its estimated work.  The waves that
 // share a SIMD then keep pace with each other (a wave that runs ahead yields
 // issue slots to the ones behind) instead of the oldest finishing first and
 // the last running alone, with too few waves to hide its latencies.
@@ -179,7 +179,7 @@ void append_ops(std::string& s, const Plan& p, int llr_type) {
     cost[(size_t)i] = op_cost(code, st, L.vtop && st == p.log2n - 1 && code <= DOP_G0R);
     total += cost[(size_t)i];
   }
-  static const double kSteps[3] = {0.30, 0.60, 0.85};
+  static const double kSteps[3] = {0.40, 0.65, 0.85};
   int next = 0;
   double done = 0.0;
   char line[96];
