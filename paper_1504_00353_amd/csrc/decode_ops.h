@@ -1505,7 +1505,10 @@ struct DecU : Dec<P> {
       this->template leaf_r1spc<S>(code, o, S - 1 < kTopLds ? S - 1 : kTopLds);
     }
     if constexpr ((code >= DOP_R1 && code <= DOP_SPC) || is_pair_op(code)) this->settle();
-    wave_sync();
+    // Ops on nodes of size <= 64 touch only registers and the output row
+    // (FLUSH aside), so consecutive ones need no ordering point and the
+    // compiler may interleave them.
+    if constexpr (S > kRegStages || code == DOP_FLUSH) wave_sync();
   }
 };
 
