@@ -1070,13 +1070,16 @@ struct RegStages {
 // that read it (f/g/g_0R of each child of the root) recompute it from the
 // channel row with the root's op (fused_top), which frees its registers
 // for the next two stages and keeps a frame within 128 VGPRs and 8.2 KB of
-// LDS (N = 32768), four frames per SIMD.
+// LDS (N = 32768), four frames per SIMD.  Float codes of N >= 16384 use the
+// virtual top stage without register stages (fused_top_f32), halving their
+// LDS slot.
 template <class P, int L2N, int NREG, int VTOP = 0>
 struct DecU : Dec<P> {
   typedef Dec<P> B;
   typedef RegStages<L2N - 1 - VTOP, NREG> R;
   static_assert(NREG == 0 || (P::ELEM == 1 && L2N - VTOP - NREG >= 11), "register stages: int8, >= 2^11 LLRs");
-  static_assert(VTOP == 0 || (P::ELEM == 1 && NREG >= 1), "a virtual top stage feeds a register stage");
+  static_assert(VTOP == 0 || (P::ELEM == 1 ? NREG >= 1 : NREG == 0),
+                "a virtual top stage feeds a register stage (int8) or the top LDS stage (float)");
   uint32_t rs[R::total()];
 
   // highest alpha stage in LDS: scratch for leaves at register stages
@@ -1307,9 +1310,75 @@ struct DecU : Dec<P> {
     }
   }
 
+  // The float form of fused_top: the same two ops on float LLRs, output the
+  // LDS stage L2N-2 (float codes keep no register stages).
+  template <uint32_t XC, uint32_t YC, int O>
+  __device__ __forceinline__ void fused_top_f32() {
+    constexpr int H1 = 1 << (L2N - 1), H2 = 1 << (L2N - 2);
+    constexpr int PERIT = 256;  // 4 floats per lane
+    constexpr int IT = H2 / PERIT;
+    constexpr int U = 4;
+    static_assert(VTOP == 1 && NREG == 0 && IT % U == 0, "float fused root-child op layout");
+    const int lane = this->lane;
+    LDS float* out = (LDS float*)this->stage(L2N - 2);
+    for (int b0 = 0; b0 < IT; b0 += U) {
+      u32x4 c00[U], c01[U], c10[U], c11[U];
+      uint32_t by0[U], by1[U], bx[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j0 = (b0 + u) * PERIT + lane * 4;
+        const int sb = 4 * (b0 + u) * PERIT;  // bytes, wave-uniform
+        c00[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(this->chr, 16 * lane, sb, 0));
+        c01[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(this->chr, 16 * lane, sb + 4 * H1, 0));
+        c10[u] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(this->chr, 16 * lane, sb + 4 * H2, 0));
+        c11[u] = __builtin_bit_cast(u32x4,
+                                    __builtin_amdgcn_raw_buffer_load_b128(this->chr, 16 * lane, sb + 4 * (H2 + H1), 0));
+        by0[u] = by1[u] = bx[u] = 0;
+        if constexpr (YC == DOP_G) {  // bits of the root's left child, at j and j + H2
+          by0[u] = this->beta[j0 >> 5] >> (j0 & 31);
+          by1[u] = this->beta[(j0 + H2) >> 5] >> ((j0 + H2) & 31);
+        }
+        if constexpr (XC == DOP_G) bx[u] = this->beta[(O + j0) >> 5] >> ((O + j0) & 31);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j0 = (b0 + u) * PERIT + lane * 4;
+        uint32_t R[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float a0 = __uint_as_float(c00[u][k]), a1 = __uint_as_float(c01[u][k]);
+          const float b0v = __uint_as_float(c10[u][k]), b1 = __uint_as_float(c11[u][k]);
+          float x, y;
+          if constexpr (YC == DOP_F) {
+            x = fmin_sum(a0, a1);
+            y = fmin_sum(b0v, b1);
+          } else if constexpr (YC == DOP_G) {  // b + (-a) is exactly b - a
+            x = __fadd_rn(a1, __uint_as_float(c00[u][k] ^ ((by0[u] << (31 - k)) & 0x80000000u)));
+            y = __fadd_rn(b1, __uint_as_float(c10[u][k] ^ ((by1[u] << (31 - k)) & 0x80000000u)));
+          } else {
+            x = __fadd_rn(a1, a0);
+            y = __fadd_rn(b1, b0v);
+          }
+          float r;
+          if constexpr (XC == DOP_F)
+            r = fmin_sum(x, y);
+          else if constexpr (XC == DOP_G)
+            r = __fadd_rn(y, __uint_as_float(__float_as_uint(x) ^ ((bx[u] << (31 - k)) & 0x80000000u)));
+          else
+            r = __fadd_rn(y, x);
+          R[k] = __float_as_uint(r);
+        }
+        *(LDS u32x4*)(out + j0) = (u32x4){R[0], R[1], R[2], R[3]};
+      }
+    }
+  }
+
   template <uint32_t W, uint32_t YC>
   __device__ __forceinline__ void step_fused() {
-    fused_top<W & 0xffu, YC, (int)(W >> 16)>();
+    if constexpr (P::ELEM == 1)
+      fused_top<W & 0xffu, YC, (int)(W >> 16)>();
+    else
+      fused_top_f32<W & 0xffu, YC, (int)(W >> 16)>();
     wave_sync();
   }
 

@@ -97,7 +97,19 @@ bool write_file_atomic(const std::string& path, const std::vector<char>& data) {
 
 UnrolledLayout unrolled_layout(const Plan& p, int llr_type) {
   UnrolledLayout L;
-  if (llr_type != 0) return L;
+  if (llr_type != 0) {
+    // float: no register stages; N >= 16384 drops its largest LDS stage
+    // (virtual top stage) when no decision node sits at the top two stages
+    if (p.log2n >= 14) {
+      bool ok = true;
+      for (int i = 0; i < p.nops; ++i) {
+        const unsigned code = p.dops[i] & 0xffu, st = (p.dops[i] >> 8) & 0xffu;
+        if ((st == (unsigned)p.log2n || st == (unsigned)p.log2n - 1) && code >= DOP_R1 && code <= DOP_SPC) ok = false;
+      }
+      L.vtop = ok ? 1 : 0;
+    }
+    return L;
+  }
   if (p.log2n == 15) {
     L.nreg = 2;
     // the virtual top stage needs both children of the root to be inner

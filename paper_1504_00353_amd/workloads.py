@@ -72,6 +72,7 @@ UNROLLED_EXTRA = [
     (256, 128, 2.5, "sc", "i8"),
     (4096, 3686, 4.0, "fastssc", "f32"),
     (16384, 14746, 4.0, "fastssc", "i8"),
+    (16384, 14746, 4.0, "fastssc", "f32"),
     (32768, 16384, 2.5, "fastssc", "i8"),
 ]
 
@@ -135,3 +136,7 @@ UNROLLED_MASKS = {
     "m16k_spc13_rep13": (16384, _blocks(16384, [("SPC", 8192), ("REP", 8192)])),
     "m16k_r113_spc13": (16384, _blocks(16384, [("R1", 8192), ("SPC", 8192)])),
 }
+
+# masks whose generated kernels are also built for float LLRs (virtual top
+# stage with g_0R and inner children, and a code that keeps the stage)
+UNROLLED_MASKS_F32 = ["m32k_spc13_rep13_r013_r113", "m32k_r014_spc13_rep13", "m32k_r013_r113_rep14"]

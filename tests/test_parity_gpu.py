@@ -232,6 +232,24 @@ def _unrolled_specs():
     return [t for t in build._kernel_specs() if t[1] != "mask" and len(t) == 5]
 
 
+@pytest.mark.parametrize("name", workloads.UNROLLED_MASKS_F32)
+def test_unrolled_kernel_masks_float(name):
+    """Float LLRs on frozen sets with leaves at the top stages: the float
+    generated kernels (virtual top stage where the root's children are
+    inner) against the float32 oracle (bits and trace) and the schedule
+    kernel."""
+    n, fr = workloads.UNROLLED_MASKS[name]
+    fr = np.asarray(fr, np.uint8)
+    code = Code(frozen=fr, llr="f32", kernel="unrolled")
+    ref = Code(frozen=fr, llr="f32", kernel="schedule")
+    rng = np.random.default_rng(n + 3 * len(name))
+    l = random_llrs(rng, 24, n, "f32")
+    check_parity(code, fr, l, "fastssc", label="unrolled float mask %s" % name)
+    b1, _ = gpu_decode(code, l)
+    b0, _ = gpu_decode(ref, l)
+    assert np.array_equal(b0, b1)
+
+
 @pytest.mark.parametrize("name", sorted(workloads.UNROLLED_MASKS))
 @pytest.mark.parametrize("kind", ["i8", "i8small"])
 def test_unrolled_kernel_masks(name, kind):
