@@ -9,7 +9,8 @@ Gb/s single-core figure for this code.  Prints one JSON line:
   latency_us   p50/p99 frame latency of a batched launch (submit -> done);
   plain        the same frames decoded with one launch per frame;
   roofline     algorithmic HBM bytes (LLR in + info bits out) per launch
-               over the decode kernel's mean duration vs 8 TB/s;
+               over the decode kernel's mean duration vs 8 TB/s (and vs a
+               measured plain copy of 1 GiB);
   valu         the bound that actually holds: the kernel's vector-ALU
                instructions per frame (committed counter summary) at one
                wave64 instruction per 4 cycles on each of the 1,024 SIMDs at
@@ -116,6 +117,26 @@ def valu_view(frames, kernel, mean_kernel_ms):
     return {"bound": "alu", "valu_insts_per_frame": round(per_frame, 1), "clock_ghz": VALU_CLOCK_GHZ,
             "floor_ms": round(floor_ms, 4), "frac": round(floor_ms / mean_kernel_ms, 4),
             "what": "frames x VALU instructions x 4 cycles / 1024 SIMDs / clock, over the mean kernel time"}
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Measured HBM bandwidth of a plain device copy (bytes read + written
+    per second, GB/s): the practical ceiling beside the 8 TB/s peak."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def copy_calibration(nbytes, reps):
@@ -400,6 +421,7 @@ def main():
     mean_kernel_s = float(np.mean(kernel_ms)) / 1e3
     achieved = bytes_per_frame * frames / mean_kernel_s / 1e9
     traffic = measured_traffic(frames, args.kernel)
+    copy_gbs = copy_bandwidth()
 
     result = {
         "metric": METRIC,
@@ -428,7 +450,8 @@ def main():
                      "traffic": None if traffic is None else round(traffic),
                      "kernel": "polar_unrolled (int8)" if args.kernel == "unrolled" else "decode_kernel<int8>",
                      "bytes_per_frame": bytes_per_frame,
-                     "mean_kernel_ms": round(mean_kernel_s * 1e3, 4)},
+                     "mean_kernel_ms": round(mean_kernel_s * 1e3, 4),
+                     "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 5)},
         "valu": valu_view(frames, args.kernel, mean_kernel_s * 1e3),
     }
     if not args.no_mixed and args.kernel == "unrolled":
