@@ -213,7 +213,7 @@ def mixed_batch_bench(steps, pool_frames=4096, frames=65536, seed=3):
             "fer": round(fe / frames, 5), "launch_shape": shape}
 
 
-def serving_bench(seconds=1.0, loads=(0.1, 0.5, 0.9), seed=4, pool=64, capacity_frames=16384, streams=2):
+def serving_bench(seconds=1.0, loads=(0.1, 0.5, 0.9), seed=4, pool=64, capacity_frames=16384, streams=3):
     """Requests of 1..64 frames (code uniform over N in {1024, 4096, 32768} x
     R in {0.5, ..., 0.9}, Eb/N0 uniform 2-5 dB) with Poisson arrivals at
     fractions of the measured batch capacity, replayed by the library's

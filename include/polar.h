@@ -270,11 +270,13 @@ void polar_batch_destroy(polar_batch* batch);
  * batch.  A request is 1..n frames of one of the batch's codes, LLRs and
  * results in host memory.  Requests are admitted first come, first served
  * as soon as device slots for all their frames are free; every poll
- * retires finished steps, admits what fits and launches one step (one
- * persistent batch decode) over all admitted frames not yet launched, on a
- * free server stream, so successive steps overlap on the device and
- * requests that arrive while a step runs join the next.  Each frame is
- * decoded exactly as polar_decode would decode it alone.
+ * retires finished steps (in whatever order they finish), admits what fits
+ * and launches steps (batch decodes) over the admitted frames not yet
+ * launched while server streams are free: one step per frame length, the
+ * length of the oldest admitted request first, so steps overlap on the
+ * device, short codes do not wait for long ones, and requests that arrive
+ * while steps run join the next.  Each frame is decoded exactly as
+ * polar_decode would decode it alone.
  * Not thread safe: one thread drives a server.
  * ------------------------------------------------------------------------ */
 typedef struct polar_server polar_server; /* opaque; owned by the library */

@@ -107,6 +107,14 @@ struct Request {
   size_t stage_off = 0;     // its LLR copy in the pinned staging ring
   size_t stage_len = 0;     // bytes taken there, including a skipped end gap
   size_t stage_end = 0;     // end of its bytes in the ring
+  int64_t stage_seq = -1;   // its staging segment (allocation order)
+};
+
+// A staging allocation; segments are released in any order, the tail
+// advancing over released ones.
+struct StageSeg {
+  size_t end = 0, len = 0;
+  bool done = false;
 };
 
 struct Step {
@@ -127,6 +135,8 @@ struct polar_server {
   uint8_t* h_bits = nullptr;  // pinned mirror of the bits pool
   uint8_t* h_stage = nullptr;  // pinned staging ring for request LLRs
   size_t stage_size = 0, stage_head = 0, stage_tail = 0, stage_used = 0;
+  std::deque<StageSeg> stage_segs;  // live staging allocations, oldest first
+  int64_t stage_base = 0;           // sequence number of stage_segs.front()
   uint64_t* d_desc = nullptr;  // one descriptor region per stream
   uint64_t* h_desc = nullptr;
   int desc_cap = 0;            // frames one step can carry
@@ -154,8 +164,7 @@ void free_server(polar_server* s) {
   delete s;
 }
 
-// FIFO staging allocation (requests are staged, launched and retired in
-// submission order, so their staging is released in the same order).
+// Staging allocation at the head of the ring (release: stage_release).
 bool stage_alloc(polar_server* s, size_t bytes, size_t* off, size_t* taken) {
   bytes = (bytes + 255) & ~(size_t)255;
   if (bytes > s->stage_size || s->stage_used + bytes > s->stage_size) return false;
@@ -183,8 +192,14 @@ bool stage_alloc(polar_server* s, size_t bytes, size_t* off, size_t* taken) {
 }
 
 void stage_release(polar_server* s, const Request& r) {
-  s->stage_used -= r.stage_len;
-  s->stage_tail = r.stage_end == s->stage_size ? 0 : r.stage_end;
+  s->stage_segs[(size_t)(r.stage_seq - s->stage_base)].done = true;
+  while (!s->stage_segs.empty() && s->stage_segs.front().done) {
+    const StageSeg& g = s->stage_segs.front();
+    s->stage_used -= g.len;
+    s->stage_tail = g.end == s->stage_size ? 0 : g.end;
+    s->stage_segs.pop_front();
+    ++s->stage_base;
+  }
   if (s->stage_used == 0) s->stage_head = s->stage_tail = 0;
 }
 
@@ -200,25 +215,26 @@ void admit(polar_server* s) {
   }
 }
 
-polar_status launch(polar_server* s) {
-  if (s->admitted.empty()) return POLAR_OK;
-  int st = -1;
-  for (size_t i = 0; i < s->busy.size(); ++i)
-    if (!s->busy[i]) {
-      st = (int)i;
-      break;
-    }
-  if (st < 0) return POLAR_OK;
+// One step over the admitted requests of length class ci (oldest first) on
+// stream st.
+polar_status launch_class(polar_server* s, int ci, int st) {
   hipStream_t stream = s->streams[st];
   uint64_t* hd = s->h_desc + 2 * (size_t)s->desc_cap * st;
   uint64_t* dd = s->d_desc + 2 * (size_t)s->desc_cap * st;
   Step step;
   step.stream = st;
   int nd = 0;
+  std::deque<int64_t> rest;
+  bool full = false;
   while (!s->admitted.empty()) {
     const int64_t id = s->admitted.front();
+    s->admitted.pop_front();
     Request& r = s->reqs[id];
-    if (nd + r.nframes > s->desc_cap) break;
+    if (r.cls != ci || full || nd + r.nframes > s->desc_cap) {
+      if (r.cls == ci) full = true;  // keep the class in order
+      rest.push_back(id);
+      continue;
+    }
     const SizeClass& c = s->cls[r.cls];
     const size_t llr_off = c.llr_base + (size_t)r.slot * c.llr_bytes;
     const size_t bits_off = c.bits_base + (size_t)r.slot * c.bits_bytes;
@@ -245,8 +261,8 @@ polar_status launch(polar_server* s) {
       ++nd;
     }
     step.reqs.push_back(id);
-    s->admitted.pop_front();
   }
+  s->admitted.swap(rest);
   if (nd == 0) return POLAR_OK;
   if (hipMemcpyAsync(dd, hd, (size_t)nd * 16, hipMemcpyHostToDevice, stream) != hipSuccess) return POLAR_EDEVICE;
   if (polar_batch_decode_desc(s->batch, dd, nd, s->d_llr, s->d_bits, stream) != POLAR_OK) return POLAR_EDEVICE;
@@ -287,13 +303,34 @@ polar_status launch(polar_server* s) {
   return POLAR_OK;
 }
 
-// Retires finished steps in launch order; appends their request ids (to
+// Launches steps while streams are free: each over one length class, the
+// class of the oldest admitted request first, so short codes do not wait
+// for the decodes of long ones.
+polar_status launch(polar_server* s) {
+  while (!s->admitted.empty()) {
+    int st = -1;
+    for (size_t i = 0; i < s->busy.size(); ++i)
+      if (!s->busy[i]) {
+        st = (int)i;
+        break;
+      }
+    if (st < 0) return POLAR_OK;
+    const polar_status e = launch_class(s, s->reqs[s->admitted.front()].cls, st);
+    if (e != POLAR_OK) return e;
+  }
+  return POLAR_OK;
+}
+
+// Retires finished steps (in any order); appends their request ids (to
 // done while cap allows, and to all when given).
 polar_status retire(polar_server* s, int64_t* done, int cap, int* ndone, std::vector<int64_t>* all = nullptr) {
-  while (!s->inflight.empty()) {
-    Step& step = s->inflight.front();
+  for (auto si = s->inflight.begin(); si != s->inflight.end();) {
+    Step& step = *si;
     const hipError_t q = hipEventQuery(step.done);
-    if (q == hipErrorNotReady) break;
+    if (q == hipErrorNotReady) {
+      ++si;
+      continue;
+    }
     if (q != hipSuccess) return POLAR_EDEVICE;
     for (int64_t id : step.reqs) {
       auto it = s->reqs.find(id);
@@ -311,7 +348,7 @@ polar_status retire(polar_server* s, int64_t* done, int cap, int* ndone, std::ve
       s->reqs.erase(it);
     }
     s->busy[step.stream] = false;
-    s->inflight.pop_front();
+    si = s->inflight.erase(si);
   }
   return POLAR_OK;
 }
@@ -421,8 +458,21 @@ polar_status polar_server_submit(polar_server* s, int code_index, int nframes, c
   if (llr_on_device) {
     r.dev_llr = (const uint8_t*)llr;
   } else {
+    const size_t head0 = s->stage_head, tail0 = s->stage_tail, used0 = s->stage_used;
     if (!stage_alloc(s, bytes, &r.stage_off, &r.stage_len)) return polar_set_status(POLAR_EAGAIN);
     r.stage_end = r.stage_off + ((bytes + 255) & ~(size_t)255);
+    try {
+      StageSeg g;
+      g.end = r.stage_end;
+      g.len = r.stage_len;
+      s->stage_segs.push_back(g);
+    } catch (const std::bad_alloc&) {
+      s->stage_head = head0;  // undo the allocation
+      s->stage_tail = tail0;
+      s->stage_used = used0;
+      return polar_set_status(POLAR_ENOMEM);
+    }
+    r.stage_seq = s->stage_base + (int64_t)s->stage_segs.size() - 1;
     memcpy(s->h_stage + r.stage_off, llr, bytes);
   }
   try {
