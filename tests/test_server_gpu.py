@@ -153,3 +153,31 @@ def test_server_device_outputs_and_trace_replay(serving):
     torch.cuda.synchronize()
     assert all(torch.equal(a, b) for a, b in zip(outs, outs2))
     srv.close()
+
+
+def test_server_short_code_not_behind_long(serving):
+    """Steps are per frame length: a one-frame request of the shortest code,
+    submitted right after a 64-frame request of the longest, is reported
+    done no later than it (and both equal the oracle)."""
+    codes, batch, frozens = serving
+    ns = [c.n for c in codes]
+    big, small = int(np.argmax(ns)), int(np.argmin(ns))
+    _, _, lb = make_frames(frozens[big], 71, 64, 4.0, "i8")
+    _, _, ls = make_frames(frozens[small], 72, 1, 4.0, "i8")
+    srv = Server(batch, slots_per_class=256, streams=3)
+    bb = np.zeros((64, codes[big].row_bytes), np.uint8)
+    bs = np.zeros((1, codes[small].row_bytes), np.uint8)
+    ib = srv.submit(big, lb, bb)
+    isml = srv.submit(small, ls, bs)
+    seen = {}
+    polls = 0
+    while len(seen) < 2:
+        for rid in srv.poll():
+            seen[rid] = polls
+        polls += 1
+        assert polls < 5_000_000, "requests not completed"
+    srv.drain()
+    srv.close()
+    assert seen[isml] <= seen[ib]
+    assert np.array_equal(bb, oracle_rows(frozens[big], lb))
+    assert np.array_equal(bs, oracle_rows(frozens[small], ls))
