@@ -230,7 +230,9 @@ polar_status polar_batch_prepare(polar_batch* batch);
  * bits base pointer; the frame's ceil(K/8) output bytes follow).  Host
  * arrays, copied.  The library orders frames longest code first and keeps
  * the descriptors in device memory it owns (allocated here, grown when
- * needed).  Synchronous.  Errors: POLAR_EINVAL (index or offset out of
+ * needed).  Synchronous: waits for the device to finish its work first
+ * (decodes in flight read the previous descriptors), so not for use under
+ * stream capture.  Errors: POLAR_EINVAL (index or offset out of
  * range), POLAR_ESTATE (not prepared), POLAR_ENOMEM, POLAR_EDEVICE. */
 polar_status polar_batch_set_frames(polar_batch* batch, int nframes, const int32_t* code_index,
                                     const int64_t* llr_offset, const int64_t* bits_offset);

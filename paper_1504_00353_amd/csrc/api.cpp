@@ -438,6 +438,8 @@ polar_status polar_batch_set_frames(polar_batch* b, int nframes, const int32_t* 
   } catch (const std::bad_alloc&) {
     return set(POLAR_ENOMEM);
   }
+  // decodes still running may read the old descriptors
+  if (hipDeviceSynchronize() != hipSuccess) return set(POLAR_EDEVICE);
   if (nframes > b->desc_cap) {
     unsigned long long* d = nullptr;
     if (hipMalloc((void**)&d, desc.size() * sizeof(unsigned long long)) != hipSuccess) return set(POLAR_ENOMEM);
