@@ -323,6 +323,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-code batch measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-server measurement")
     ap.add_argument("--serving-seconds", type=float, default=1.0)
+    ap.add_argument("--host-steps", type=int, default=10, help="steps of the PCIe-inclusive measurement (0: skip)")
     ap.add_argument("--prewarm-seconds", type=float, default=0.25,
                     help="untimed decode launches before the warmup steps, so the timed steps run at the "
                          "GPU's steady clock (short runs start below it)")
@@ -417,6 +418,30 @@ def main():
                  "latency_us": {"p50": round(percentile(plat, 50), 2), "p99": round(percentile(plat, 99), 2)},
                  "bits_equal_batched": True}
 
+    # host-inclusive: LLRs from pinned host memory, bits back to it (PCIe), per step
+    host = None
+    if args.host_steps > 0:
+        h_llr = torch.from_numpy(llr_np).pin_memory()
+        h_out = torch.empty((frames, code.row_bytes), dtype=torch.uint8).pin_memory()
+        d_llr = torch.empty_like(llr)
+        for _ in range(2):
+            d_llr.copy_(h_llr, non_blocking=True)
+            code.decode(d_llr, out=out)
+            h_out.copy_(out, non_blocking=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.host_steps):
+            d_llr.copy_(h_llr, non_blocking=True)
+            code.decode(d_llr, out=out)
+            h_out.copy_(out, non_blocking=True)
+        torch.cuda.synchronize()
+        hw = (time.perf_counter() - t) / args.host_steps
+        assert torch.equal(h_out, out.cpu()), "host-inclusive decode differs"
+        host = {"value": round(float(k) * frames / hw / 1e9, 3), "unit": "Gbps", "ms_per_step": round(hw * 1e3, 4),
+                "what": "pinned host LLRs -> device, decode, bits -> pinned host, one stream (PCIe-inclusive; "
+                        "not the headline value)"}
+        del h_llr, h_out, d_llr
+
     bytes_per_frame = n * 1 + (k + 7) // 8
     mean_kernel_s = float(np.mean(kernel_ms)) / 1e3
     achieved = bytes_per_frame * frames / mean_kernel_s / 1e9
@@ -444,6 +469,7 @@ def main():
         {"p50": round(percentile(lat, 50), 2), "p99": round(percentile(lat, 99), 2),
          "what": "batched launch of %d frames, submit to completion" % frames},
         "plain": plain,
+        "host_inclusive": host,
         "fer": fer,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5),
