@@ -50,8 +50,10 @@ typedef enum { POLAR_ALGO_FASTSSC = 0, POLAR_ALGO_SC = 1 } polar_algo;
 typedef enum { POLAR_LLR_I8 = 0, POLAR_LLR_F32 = 1 } polar_llr;
 
 /* Which kernel decodes a code (Sec. III-A vs III-B: instruction-based vs
- * unrolled decoder).  Both run the same node functions on the same data
- * layout and give identical results.
+ * unrolled decoder).  Both run the same node functions and give identical
+ * results; the unrolled kernels of N >= 16384 also lay out the widest LLR
+ * stages differently (registers, or recomputed from the channel) to fit
+ * more frames on a compute unit.
  *   POLAR_KERNEL_SCHEDULE: one kernel for every code reads the code's
  *     schedule from device memory at run time; prepare is immediate.
  *   POLAR_KERNEL_UNROLLED: a kernel generated for this one code, with the
