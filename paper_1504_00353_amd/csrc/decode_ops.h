@@ -1048,19 +1048,22 @@ struct Dec {
 // its own stage and offset (Sec. III-B.4).  int8 codes may keep their NREG
 // top alpha stages (L2N-1 down to L2N-NREG, each >= 2^11 LLRs) in registers
 // instead of LDS, which cuts a frame's LDS footprint (N = 32768: 36.9 KB ->
-// 12.3 KB) so that more frames share a compute unit.  Register stages use
+// 12.3 KB) so that more frames share a compute unit; float codes of
+// N >= 16384 keep one (L2N-2, below a virtual top stage).  Register stages use
 // the chunked layout of the wide F/G ops: LLR e of stage s sits in lane
 // (e >> 4) & 63, register 4 (e >> 10) + ((e >> 2) & 3), byte e & 3, so the
-// pair e, e + 2^(s-1) of f and g is always lane-local.
+// pair e, e + 2^(s-1) of f and g is always lane-local.  A float register
+// stage holds LLR e in lane (e >> 2) & 63, register 4 (e >> 8) + (e & 3).
 // ---------------------------------------------------------------------------
-template <int TOP, int NREG>
+template <int TOP, int NREG, int ELEM = 1>
 struct RegStages {
   // register stages: TOP down to TOP - NREG + 1
   static constexpr bool has(int s) { return NREG > 0 && s <= TOP && s > TOP - NREG; }
   // first register of stage s: stage TOP first, then the next lower
+  // (ELEM bytes per LLR: 256 / ELEM LLRs per register across the wave)
   static constexpr int base(int s) {
     int b = 0;
-    for (int t = TOP; t > s; --t) b += (1 << t) >> 8;
+    for (int t = TOP; t > s; --t) b += ((1 << t) * ELEM) >> 8;
     return b;
   }
   static constexpr int total() { return NREG > 0 ? base(TOP - NREG) : 1; }
@@ -1071,15 +1074,17 @@ struct RegStages {
 // channel row with the root's op (fused_top), which frees its registers
 // for the next two stages and keeps a frame within 128 VGPRs and 8.2 KB of
 // LDS (N = 32768), four frames per SIMD.  Float codes of N >= 16384 use the
-// virtual top stage without register stages (fused_top_f32), halving their
-// LDS slot.
+// virtual top stage and keep the stage below it (L2N-2) in registers
+// (fused_top_f32 writes it), which cuts their LDS slot to about a quarter
+// (N = 32768: 132 KB -> 36 KB, four frames per compute unit).
 template <class P, int L2N, int NREG, int VTOP = 0>
 struct DecU : Dec<P> {
   typedef Dec<P> B;
-  typedef RegStages<L2N - 1 - VTOP, NREG> R;
-  static_assert(NREG == 0 || (P::ELEM == 1 && L2N - VTOP - NREG >= 11), "register stages: int8, >= 2^11 LLRs");
-  static_assert(VTOP == 0 || (P::ELEM == 1 ? NREG >= 1 : NREG == 0),
-                "a virtual top stage feeds a register stage (int8) or the top LDS stage (float)");
+  typedef RegStages<L2N - 1 - VTOP, NREG, P::ELEM> R;
+  static_assert(NREG == 0 || (P::ELEM == 1 ? L2N - VTOP - NREG >= 11 : (VTOP == 1 && NREG == 1 && L2N >= 14)),
+                "register stages: int8 of >= 2^11 LLRs, or one float stage below a virtual top stage");
+  static_assert(VTOP == 0 || (P::ELEM == 1 ? NREG >= 1 : NREG <= 1),
+                "a virtual top stage feeds a register stage (int8) or the top float stage");
   uint32_t rs[R::total()];
 
   // highest alpha stage in LDS: scratch for leaves at register stages
@@ -1310,17 +1315,20 @@ struct DecU : Dec<P> {
     }
   }
 
-  // The float form of fused_top: the same two ops on float LLRs, output the
-  // LDS stage L2N-2 (float codes keep no register stages).
+  // The float form of fused_top: the same two ops on float LLRs, output
+  // stage L2N-2 (the float register stage when the layout has one, else
+  // LDS).
   template <uint32_t XC, uint32_t YC, int O>
   __device__ __forceinline__ void fused_top_f32() {
     constexpr int H1 = 1 << (L2N - 1), H2 = 1 << (L2N - 2);
     constexpr int PERIT = 256;  // 4 floats per lane
     constexpr int IT = H2 / PERIT;
     constexpr int U = 4;
-    static_assert(VTOP == 1 && NREG == 0 && IT % U == 0, "float fused root-child op layout");
+    static_assert(VTOP == 1 && NREG <= 1 && IT % U == 0, "float fused root-child op layout");
+    constexpr bool DREG = R::has(L2N - 2);
     const int lane = this->lane;
     LDS float* out = (LDS float*)this->stage(L2N - 2);
+#pragma unroll
     for (int b0 = 0; b0 < IT; b0 += U) {
       u32x4 c00[U], c01[U], c10[U], c11[U];
       uint32_t by0[U], by1[U], bx[U];
@@ -1343,7 +1351,7 @@ struct DecU : Dec<P> {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j0 = (b0 + u) * PERIT + lane * 4;
-        uint32_t R[4];
+        uint32_t Rv[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const float a0 = __uint_as_float(c00[u][k]), a1 = __uint_as_float(c01[u][k]);
@@ -1366,9 +1374,19 @@ struct DecU : Dec<P> {
             r = __fadd_rn(y, __uint_as_float(__float_as_uint(x) ^ ((bx[u] << (31 - k)) & 0x80000000u)));
           else
             r = __fadd_rn(y, x);
-          R[k] = __float_as_uint(r);
+          Rv[k] = __float_as_uint(r);
         }
-        *(LDS u32x4*)(out + j0) = (u32x4){R[0], R[1], R[2], R[3]};
+        if constexpr (DREG) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            // computed here: sunk into its readers, each value would keep
+            // its four channel LLRs alive instead of one register
+            asm volatile("" : "+v"(Rv[k]));
+            rs[R::base(L2N - 2) + 4 * (b0 + u) + k] = Rv[k];
+          }
+        } else {
+          *(LDS u32x4*)(out + j0) = (u32x4){Rv[0], Rv[1], Rv[2], Rv[3]};
+        }
       }
     }
   }
@@ -1402,7 +1420,13 @@ struct DecU : Dec<P> {
         const int i0 = (b0 + u) * PERIT + lane * 4;
         bb[u] = 0;
         if (H >= PERIT || i0 < H) {
-          if constexpr (CH) {
+          if constexpr (R::has(S)) {  // block it and it + IT of this lane
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              va[u][k] = rs[R::base(S) + 4 * (b0 + u) + k];
+              vb[u][k] = rs[R::base(S) + 4 * (b0 + u + IT) + k];
+            }
+          } else if constexpr (CH) {
             va[u] = __builtin_bit_cast(
                 u32x4, __builtin_amdgcn_raw_buffer_load_b128(this->chr, 16 * lane, 4 * (b0 + u) * PERIT, 0));
             vb[u] = __builtin_bit_cast(
@@ -1540,6 +1564,98 @@ struct DecU : Dec<P> {
     this->template finish_leaf<S, PER>(wd, code, (LDS uint32_t*)this->stage(kTopLds));
   }
 
+  // Rate-1, repetition or SPC leaf whose float LLRs are a register stage S
+  // (LLR e in lane (e >> 2) & 63, register 4 (e >> 8) + (e & 3)).
+  template <int S>
+  __device__ __forceinline__ void leaf_reg_f32(uint32_t code, int o) {
+    constexpr int NV = 1 << S;
+    constexpr int NB = NV >> 8;  // blocks of 256 LLRs, 4 registers each
+    constexpr int NW = NV >> 5;
+    constexpr int PER = NW / 64;
+    static_assert(PER >= 1, "a float register stage holds >= 2048 LLRs");
+    const int lane = this->lane;
+    LDS uint32_t* bw = this->beta + (o >> 5);
+    if (this->tr) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) this->tr[o + 256 * b + 4 * lane + k] = __uint_as_float(rs[R::base(S) + 4 * b + k]);
+    }
+    if (code == DOP_REP) {
+      // the halving tree s_i <- s_i + s_{i+d}, d = NV/2 .. 1, one rounded add each
+      float v[4 * NB];
+#pragma unroll
+      for (int r = 0; r < 4 * NB; ++r) v[r] = __uint_as_float(rs[R::base(S) + r]);
+#pragma unroll
+      for (int nb = NB / 2; nb >= 1; nb /= 2)  // d = 256 nb: register r + 4 nb of the same lane
+#pragma unroll
+        for (int r = 0; r < 4 * nb; ++r) v[r] = __fadd_rn(v[r], v[r + 4 * nb]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {  // d = 128 .. 4: lane + d / 4
+        v[k] = __fadd_rn(v[k], from_up<32>(v[k]));
+        v[k] = __fadd_rn(v[k], from_up<16>(v[k]));
+        v[k] = __fadd_rn(v[k], from_up<8>(v[k]));
+        v[k] = __fadd_rn(v[k], from_up<4>(v[k]));
+        v[k] = __fadd_rn(v[k], from_up<2>(v[k]));
+        v[k] = __fadd_rn(v[k], from_up<1>(v[k]));
+      }
+      v[0] = __fadd_rn(v[0], v[2]);  // d = 2, 1: in lane 0
+      v[1] = __fadd_rn(v[1], v[3]);
+      v[0] = __fadd_rn(v[0], v[1]);
+      const bool bit = rflf(v[0]) < 0.0f;
+      for (int j = lane; j < NW; j += 64) bw[j] = bit ? ~0u : 0u;
+      this->pend_v = bit ? 1ull : 0ull;
+      this->pend_n = 1;
+      return;
+    }
+    // beta words to LDS: in block b, lane L holds the hard decisions of LLRs
+    // 4L .. 4L+3, a nibble of word 8b + L/8
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      uint32_t nib = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) nib |= (__uint_as_float(rs[R::base(S) + 4 * b + k]) < 0.0f ? 1u : 0u) << k;
+      uint32_t t = nib << (4 * (lane & 7));
+      t |= from_up<4>(t);
+      t |= from_up<2>(t);
+      t |= from_up<1>(t);
+      if ((lane & 7) == 0) bw[8 * b + (lane >> 3)] = t;
+    }
+    wave_sync();
+    uint32_t wd[PER];
+    int par = 0;
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      wd[m] = bw[lane + 64 * m];
+      par ^= __popc(wd[m]);
+    }
+    if (code == DOP_SPC && (__popcll(ballot((par & 1) != 0)) & 1)) {
+      float best = 3.0e38f;
+      int bi = 0x7fffffff;
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float m = fabsf(__uint_as_float(rs[R::base(S) + 4 * b + k]));
+          if (m < best) {  // this lane's indices grow in this order
+            best = m;
+            bi = 256 * b + 4 * lane + k;
+          }
+        }
+      const int idx = this->argmin_reduce(best, bi);
+      const int jw = idx >> 5;
+      if ((jw & 63) == lane) {
+#pragma unroll
+        for (int m = 0; m < PER; ++m)
+          if (m == (jw >> 6)) {
+            wd[m] ^= 1u << (idx & 31);
+            bw[jw] = wd[m];
+          }
+      }
+    }
+    this->template finish_leaf<S, PER>(wd, code, (LDS uint32_t*)this->stage(kTopLds));
+  }
+
   // ----------------------------------------------------------- one op
   template <uint32_t W>
   __device__ __forceinline__ void step_c() {
@@ -1567,7 +1683,10 @@ struct DecU : Dec<P> {
     } else if constexpr (code <= DOP_CR0) {
       this->big_combine(code, S, o);
     } else if constexpr (R::has(S)) {
-      leaf_reg<S>(code, o);
+      if constexpr (P::ELEM == 1)
+        leaf_reg<S>(code, o);
+      else
+        leaf_reg_f32<S>(code, o);
     } else if constexpr (code == DOP_REP) {
       this->big_leaf(code, S, o);
     } else {

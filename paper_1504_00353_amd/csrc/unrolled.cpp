@@ -98,8 +98,9 @@ bool write_file_atomic(const std::string& path, const std::vector<char>& data) {
 UnrolledLayout unrolled_layout(const Plan& p, int llr_type) {
   UnrolledLayout L;
   if (llr_type != 0) {
-    // float: no register stages; N >= 16384 drops its largest LDS stage
-    // (virtual top stage) when no decision node sits at the top two stages
+    // float: N >= 16384 drops its largest LDS stage (virtual top stage) when
+    // no decision node sits at the top two stages, and keeps the next one
+    // in registers
     if (p.log2n >= 14) {
       bool ok = true;
       for (int i = 0; i < p.nops; ++i) {
@@ -107,6 +108,7 @@ UnrolledLayout unrolled_layout(const Plan& p, int llr_type) {
         if ((st == (unsigned)p.log2n || st == (unsigned)p.log2n - 1) && code >= DOP_R1 && code <= DOP_SPC) ok = false;
       }
       L.vtop = ok ? 1 : 0;
+      L.nreg = L.vtop;  // and the stage below it in registers
     }
     return L;
   }
