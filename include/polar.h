@@ -185,7 +185,8 @@ polar_status polar_encode(const polar_code* code, const uint8_t* info, int nfram
  * Both buffers belong to the caller and must stay alive until the stream
  * has run the decode.  llr must be 4-byte aligned (16 recommended).
  * nframes == 0 is a no-op.  Errors: POLAR_EINVAL (NULL buffers with
- * nframes > 0, nframes < 0, misaligned llr), POLAR_ESTATE (not prepared),
+ * nframes > 0, nframes < 0, misaligned llr), POLAR_ESTATE (not prepared,
+ * or the current device is not the one the code was prepared on),
  * POLAR_EDEVICE (launch failed).  Kernel faults surface at the caller's
  * next synchronisation. */
 polar_status polar_decode(const polar_code* code, const void* llr, int nframes, uint8_t* bits,
@@ -243,8 +244,8 @@ polar_status polar_batch_set_frames(polar_batch* batch, int nframes, const int32
  * the given stream.  Asynchronous; never allocates or synchronises, so it
  * can be captured in a HIP graph (the descriptors must not change between
  * capture and replay).  llr: device memory of the batch's LLR type, 4-byte
- * aligned; bits: device memory.  Errors: POLAR_EINVAL, POLAR_ESTATE,
- * POLAR_EDEVICE. */
+ * aligned; bits: device memory.  Errors: POLAR_EINVAL, POLAR_ESTATE (not
+ * prepared, or the current device is not the batch's), POLAR_EDEVICE. */
 polar_status polar_batch_decode(const polar_batch* batch, const void* llr, uint8_t* bits, void* stream);
 
 /* As polar_batch_decode with caller-owned descriptors in device memory:
@@ -281,7 +282,10 @@ void polar_batch_destroy(polar_batch* batch);
  * device, short codes do not wait for long ones, and requests that arrive
  * while steps run join the next.  Each frame is decoded exactly as
  * polar_decode would decode it alone.
- * Not thread safe: one thread drives a server.
+ * Not thread safe: one thread drives a server, with the server's device
+ * current.  After a HIP failure (POLAR_EDEVICE from a poll) the requests in
+ * flight are lost and every later submit or poll returns POLAR_EDEVICE:
+ * destroy the server.
  * ------------------------------------------------------------------------ */
 typedef struct polar_server polar_server; /* opaque; owned by the library */
 
@@ -293,7 +297,8 @@ typedef struct polar_server polar_server; /* opaque; owned by the library */
  * memory holding submitted LLRs until their step has copied them.
  * Allocates device and pinned host memory.  NULL on error (see
  * polar_last_status: POLAR_EINVAL, POLAR_ESTATE if the batch is not
- * prepared, POLAR_ENOMEM, POLAR_EDEVICE). */
+ * prepared or was prepared on another device, POLAR_ENOMEM,
+ * POLAR_EDEVICE). */
 polar_server* polar_server_create(const polar_batch* batch, const polar_code* const* codes, int ncodes,
                                   int slots_per_class, int streams, size_t staging_bytes);
 
@@ -311,7 +316,8 @@ enum { POLAR_SERVER_LLR_DEVICE = 1, POLAR_SERVER_BITS_DEVICE = 2 };
  * decode).  Buffers must stay valid until the request is reported done.
  * *id receives the request id (> 0).  Errors: POLAR_EINVAL (bad arguments,
  * or more frames than the code's length class has slots), POLAR_EAGAIN
- * (staging memory full: poll, then submit again). */
+ * (staging memory full: poll, then submit again), POLAR_EDEVICE (the
+ * server has failed). */
 polar_status polar_server_submit(polar_server* server, int code_index, int nframes, const void* llr, int where,
                                  uint8_t* bits, int64_t* id);
 
@@ -322,7 +328,7 @@ polar_status polar_server_submit(polar_server* server, int code_index, int nfram
  * non-decreasing), and the server is polled continuously;
  * completion_s[i] receives the time (same clock) at which a poll saw it
  * done.  Returns when every request is done.  Errors: POLAR_EINVAL,
- * POLAR_EDEVICE. */
+ * POLAR_ESTATE (another device is current), POLAR_EDEVICE. */
 polar_status polar_server_run_trace(polar_server* server, int nreq, const double* arrival_s,
                                     const int32_t* code_index, const int32_t* nframes, const void* const* llr,
                                     uint8_t* const* bits, double* completion_s);
@@ -330,7 +336,8 @@ polar_status polar_server_run_trace(polar_server* server, int nreq, const double
 /* Makes progress without blocking: retires finished steps (writing their
  * requests' bits), admits waiting requests, launches a step.  Writes the
  * ids of requests completed by this call to done_ids (at most cap; *ndone
- * receives the count).  Errors: POLAR_EINVAL, POLAR_EDEVICE. */
+ * receives the count).  Errors: POLAR_EINVAL, POLAR_ESTATE (another device
+ * is current), POLAR_EDEVICE. */
 polar_status polar_server_poll(polar_server* server, int64_t* done_ids, int cap, int* ndone);
 
 /* Requests waiting for slots, admitted but not launched, and steps in

@@ -34,6 +34,13 @@ polar_status set_msg(polar_status s, const std::string& msg) {
   return s;
 }
 
+// Kernels of a code or batch are loaded on the device it was prepared on;
+// launches go to the caller's current device.
+bool on_device(int dev) {
+  int cur = -1;
+  return hipGetDevice(&cur) == hipSuccess && cur == dev;
+}
+
 int log2_exact(int n) {
   if (n < 2 || n > polar::kMaxN || (n & (n - 1))) return -1;
   int l = 0;
@@ -299,6 +306,7 @@ static polar_status decode_impl(const polar_code* c, const void* llr, int nframe
   if (!llr || !bits) return set(POLAR_EINVAL);
   if (((uintptr_t)llr & 3u) != 0) return set(POLAR_EINVAL);
   if (c->llr_type == POLAR_LLR_F32 && trace && ((uintptr_t)trace & 3u) != 0) return set(POLAR_EINVAL);
+  if (!on_device(c->device)) return set_msg(POLAR_ESTATE, "the current device is not the one the code was prepared on");
   const int rc = c->kernel == POLAR_KERNEL_UNROLLED
                      ? polar::unrolled_launch(c->unrolled, llr, nframes, bits, trace, c->waves_per_block, stream)
                      : polar::launch_decode(c->d_ops, c->nops, c->plan.log2n, c->plan.k, c->llr_type, llr, nframes,
@@ -460,6 +468,8 @@ polar_status polar_batch_decode_desc(const polar_batch* b, const uint64_t* desc,
   if (!b->prepared) return set(POLAR_ESTATE);
   if (nframes == 0) return set(POLAR_OK);
   if (!desc || !llr || !bits || ((uintptr_t)llr & 3u) != 0) return set(POLAR_EINVAL);
+  if (!on_device(b->device))
+    return set_msg(POLAR_ESTATE, "the current device is not the one the batch was prepared on");
   const int rc = polar::batch_launch(b->fn, desc, nframes, llr, bits, b->wave_bytes, b->waves_per_block, b->blocks,
                                      stream);
   return set(rc == 0 ? POLAR_OK : POLAR_EDEVICE);
@@ -475,6 +485,8 @@ polar_status polar_batch_tune(polar_batch* b, const void* llr, uint8_t* bits, vo
   if (!b->prepared) return set(POLAR_ESTATE);
   if (b->nframes == 0) return set(POLAR_OK);
   if (!llr || !bits) return set(POLAR_EINVAL);
+  if (!on_device(b->device))
+    return set_msg(POLAR_ESTATE, "the current device is not the one the batch was prepared on");
   int lds_max = 0;
   if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) != hipSuccess)
     return set(POLAR_EDEVICE);

@@ -127,6 +127,8 @@ struct Step {
 
 struct polar_server {
   const polar_batch* batch = nullptr;
+  int device = 0;       // the batch's device: every launch goes there
+  bool failed = false;  // a HIP call failed: requests in flight are lost
   int elem = 1;
   std::vector<int> code_n, code_rb, code_cls;
   std::vector<SizeClass> cls;
@@ -151,6 +153,15 @@ struct polar_server {
 };
 
 namespace {
+
+// Device work is only valid on the batch's device, and after a failed HIP
+// call the server's steps are in an unknown state.
+polar_status usable(const polar_server* s) {
+  if (s->failed) return POLAR_EDEVICE;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != s->device) return POLAR_ESTATE;
+  return POLAR_OK;
+}
 
 void free_server(polar_server* s) {
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
@@ -370,10 +381,13 @@ polar_server* polar_server_create(const polar_batch* batch, const polar_code* co
     return nullptr;
   }
   polar_status st = POLAR_OK;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != batch->device) st = POLAR_ESTATE;
   try {
     s->batch = batch;
+    s->device = batch->device;
     s->elem = batch->llr_type == POLAR_LLR_F32 ? 4 : 1;
-    for (int i = 0; i < ncodes; ++i) {
+    for (int i = 0; i < ncodes && st == POLAR_OK; ++i) {
       if (!codes[i] || codes[i]->plan.n != batch->plans[i].n || codes[i]->plan.frozen != batch->plans[i].frozen) {
         st = POLAR_EINVAL;
         break;
@@ -445,6 +459,7 @@ polar_status polar_server_submit(polar_server* s, int code_index, int nframes, c
   const int llr_on_device = where & POLAR_SERVER_LLR_DEVICE;
   if (!s || code_index < 0 || code_index >= (int)s->code_n.size() || nframes < 1 || !llr || !bits || !id)
     return polar_set_status(POLAR_EINVAL);
+  if (s->failed) return polar_set_status(POLAR_EDEVICE);
   const SizeClass& c = s->cls[s->code_cls[code_index]];
   if (nframes > c.ring.n) return polar_set_status(POLAR_EINVAL);  // could never be admitted
   if (llr_on_device && ((uintptr_t)llr % (uintptr_t)s->elem) != 0) return polar_set_status(POLAR_EINVAL);
@@ -489,12 +504,18 @@ polar_status polar_server_submit(polar_server* s, int code_index, int nframes, c
 polar_status polar_server_poll(polar_server* s, int64_t* done_ids, int cap, int* ndone) {
   if (!s || cap < 0 || !ndone) return polar_set_status(POLAR_EINVAL);
   *ndone = 0;
+  const polar_status u = usable(s);
+  if (u != POLAR_OK) return polar_set_status(u);
   try {
     polar_status st = retire(s, done_ids, cap, ndone);
-    if (st != POLAR_OK) return polar_set_status(st);
-    admit(s);
-    st = launch(s);
-    if (st != POLAR_OK) return polar_set_status(st);
+    if (st == POLAR_OK) {
+      admit(s);
+      st = launch(s);
+    }
+    if (st != POLAR_OK) {
+      s->failed = true;
+      return polar_set_status(st);
+    }
   } catch (const std::bad_alloc&) {
     return polar_set_status(POLAR_ENOMEM);
   }
@@ -506,6 +527,8 @@ polar_status polar_server_run_trace(polar_server* s, int nreq, const double* arr
                                     double* completion_s) {
   if (!s || nreq < 0 || (nreq > 0 && (!arrival_s || !code_index || !nframes || !llr || !bits || !completion_s)))
     return polar_set_status(POLAR_EINVAL);
+  const polar_status u = usable(s);
+  if (u != POLAR_OK) return polar_set_status(u);
   typedef std::chrono::steady_clock clk;
   const clk::time_point t0 = clk::now();
   auto since = [&]() { return std::chrono::duration<double>(clk::now() - t0).count(); };
@@ -525,10 +548,14 @@ polar_status polar_server_run_trace(polar_server* s, int nreq, const double* arr
       done.clear();
       int nd = 0;
       polar_status st = retire(s, nullptr, 0, &nd, &done);
-      if (st != POLAR_OK) return polar_set_status(st);
-      admit(s);
-      st = launch(s);
-      if (st != POLAR_OK) return polar_set_status(st);
+      if (st == POLAR_OK) {
+        admit(s);
+        st = launch(s);
+      }
+      if (st != POLAR_OK) {
+        s->failed = true;
+        return polar_set_status(st);
+      }
       if (!done.empty()) {
         const double t = since();
         for (int64_t id : done) {
