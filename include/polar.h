@@ -231,8 +231,8 @@ polar_status polar_batch_prepare(polar_batch* batch);
  * llr_offset[i] (elements from the llr base pointer of the decode; the
  * frame's N LLRs follow contiguously) and bits_offset[i] (bytes from the
  * bits base pointer; the frame's ceil(K/8) output bytes follow).  Host
- * arrays, copied.  The library orders frames longest code first and keeps
- * the descriptors in device memory it owns (allocated here, grown when
+ * arrays, copied.  The library orders frames longest code first, frames
+ * of one code together (in their given order), and keeps the descriptors in device memory it owns (allocated here, grown when
  * needed).  Synchronous: waits for the device to finish its work first
  * (decodes in flight read the previous descriptors), so not for use under
  * stream capture.  Errors: POLAR_EINVAL (index or offset out of

@@ -150,6 +150,7 @@ struct polar_server {
   std::deque<Step> inflight;
   std::unordered_map<int64_t, Request> reqs;
   int64_t next_id = 1;
+  std::vector<uint64_t> sort_tmp;  // scratch of group_by_code
 };
 
 namespace {
@@ -228,6 +229,25 @@ void admit(polar_server* s) {
 
 // One step over the admitted requests of length class ci (oldest first) on
 // stream st.
+// Stable counting sort of nd descriptors (pairs of words, code index in the
+// low byte of the first) by code, so that neighbouring waves of the step
+// run the same decoder.
+void group_by_code(uint64_t* d, int nd, int ncodes, std::vector<uint64_t>& tmp) {
+  int count[257] = {0};
+  for (int j = 0; j < nd; ++j) ++count[(d[2 * j] & 255u) + 1];
+  int used = 0;
+  for (int c = 1; c <= ncodes; ++c) used += count[c] ? 1 : 0;
+  if (used < 2) return;
+  for (int c = 0; c < ncodes; ++c) count[c + 1] += count[c];
+  tmp.resize(2 * (size_t)nd);
+  for (int j = 0; j < nd; ++j) {
+    const int k = count[d[2 * j] & 255u]++;
+    tmp[2 * (size_t)k] = d[2 * j];
+    tmp[2 * (size_t)k + 1] = d[2 * j + 1];
+  }
+  std::copy(tmp.begin(), tmp.end(), d);
+}
+
 polar_status launch_class(polar_server* s, int ci, int st) {
   hipStream_t stream = s->streams[st];
   uint64_t* hd = s->h_desc + 2 * (size_t)s->desc_cap * st;
@@ -275,6 +295,7 @@ polar_status launch_class(polar_server* s, int ci, int st) {
   }
   s->admitted.swap(rest);
   if (nd == 0) return POLAR_OK;
+  group_by_code(hd, nd, (int)s->code_n.size(), s->sort_tmp);
   if (hipMemcpyAsync(dd, hd, (size_t)nd * 16, hipMemcpyHostToDevice, stream) != hipSuccess) return POLAR_EDEVICE;
   if (polar_batch_decode_desc(s->batch, dd, nd, s->d_llr, s->d_bits, stream) != POLAR_OK) return POLAR_EDEVICE;
   // results to pinned host memory: one copy per slot range of each length
@@ -418,6 +439,7 @@ polar_server* polar_server_create(const polar_batch* batch, const polar_code* co
         c.ring.init(slots_per_class);
       }
       s->desc_cap = slots_per_class * (int)s->cls.size();
+      s->sort_tmp.reserve(2 * (size_t)s->desc_cap);  // steps never allocate for it
       s->stage_size = staging_bytes;
       if (hipMalloc((void**)&s->d_llr, llr_total) != hipSuccess ||
           hipMalloc((void**)&s->d_bits, bits_total) != hipSuccess ||
