@@ -110,6 +110,36 @@ polar_status polar_set_fused_nodes(polar_code* code, int enable);
  * be called before polar_prepare(); POLAR_ESTATE afterwards. */
 polar_status polar_set_kernel(polar_code* code, int kernel);
 
+/* Layouts of an unrolled kernel's widest alpha stages (how many stages sit
+ * in registers instead of LDS, and whether the stage below the root is
+ * recomputed from the channel instead of stored): the choices the
+ * autotuner times, a per-code analogue of the threads-per-block,
+ * blocks-per-kernel and shared-memory sweeps of Sec. V (Sec. V-B, V-C,
+ * V-E).  Index 0 is the default rule;
+ * every layout gives identical results.  polar_layout_count returns how
+ * many there are for the code as configured (LLR type; 0 on NULL),
+ * polar_layout_info describes one (any output pointer may be NULL;
+ * wave_lds_bytes: LDS per frame).  Errors: POLAR_EINVAL. */
+int polar_layout_count(const polar_code* code);
+polar_status polar_layout_info(const polar_code* code, int index, int* reg_stages, int* virtual_top,
+                               int* wave_lds_bytes);
+
+/* Selects layout `index` for the code's unrolled kernel (and for batches
+ * created from the code afterwards).  Before polar_prepare.  Errors:
+ * POLAR_EINVAL (index out of range), POLAR_ESTATE (prepared). */
+polar_status polar_set_layout(polar_code* code, int index);
+
+/* Autotuner for one code: prepares the code with each layout in turn
+ * (compiling kernels not yet in the cache), times decodes of the given
+ * frames (device buffers as for polar_decode; bits is overwritten), and
+ * leaves the code prepared with the fastest; *chosen (may be NULL)
+ * receives its index.  The code must use the unrolled kernel and not be
+ * prepared.  Synchronous.  Errors: POLAR_EINVAL, POLAR_ESTATE,
+ * POLAR_ECOMPILE, POLAR_EDEVICE, POLAR_ENOMEM (the code is then left
+ * unprepared, with the default layout). */
+polar_status polar_tune_layout(polar_code* code, const void* llr, int nframes, uint8_t* bits, void* stream,
+                               int* chosen);
+
 /* Generates and compiles the unrolled kernel of the code as configured
  * (algorithm and LLR type) into the kernel cache, unless it is there
  * already.  Host only: needs no device, so kernels can be built ahead of

@@ -22,7 +22,7 @@ EXPORTS = [
     "polar_construct", "polar_construct_mask", "polar_configure", "polar_prepare", "polar_destroy",
     "polar_last_status", "polar_strerror", "polar_n", "polar_k", "polar_frozen_mask", "polar_schedule",
     "polar_encode", "polar_decode", "polar_decode_trace", "polar_set_kernel", "polar_set_fused_nodes",
-    "polar_device_schedule",
+    "polar_device_schedule", "polar_layout_count", "polar_layout_info", "polar_set_layout", "polar_tune_layout",
     "polar_build_kernel",
     "polar_last_message", "polar_batch_create", "polar_batch_build_kernel", "polar_batch_prepare",
     "polar_batch_set_frames", "polar_batch_decode", "polar_batch_decode_desc", "polar_batch_tune",
@@ -59,6 +59,10 @@ def _lib():
         L.polar_set_kernel.argtypes = [P, I]
         L.polar_set_fused_nodes.argtypes = [P, I]
         L.polar_device_schedule.argtypes = [P, P, I, P]
+        L.polar_layout_count.argtypes = [P]
+        L.polar_layout_info.argtypes = [P, I, P, P, P]
+        L.polar_set_layout.argtypes = [P, I]
+        L.polar_tune_layout.argtypes = [P, P, I, P, P, P]
         L.polar_build_kernel.argtypes = [P]
         L.polar_destroy.argtypes = [P]
         L.polar_destroy.restype = None
@@ -120,7 +124,7 @@ class Code:
     """A polar code plus its decoder schedule (host) and device tables."""
 
     def __init__(self, n=None, k=None, design_db=None, algo="fastssc", llr="i8", frozen=None, prepare=True,
-                 kernel="schedule", fused=True):
+                 kernel="schedule", fused=True, layout=0):
         L = _lib()
         if frozen is not None:
             frozen = np.ascontiguousarray(frozen, dtype=np.uint8)
@@ -138,6 +142,8 @@ class Code:
         _check(L.polar_set_kernel(self._h, KERNEL[kernel]), "polar_set_kernel")
         self.fused = bool(fused)
         _check(L.polar_set_fused_nodes(self._h, 1 if fused else 0), "polar_set_fused_nodes")
+        self.layout = int(layout)
+        _check(L.polar_set_layout(self._h, self.layout), "polar_set_layout")
         self.prepared = False
         if prepare:
             self.prepare()
@@ -149,6 +155,37 @@ class Code:
     def build_kernel(self):
         """Compile this code's unrolled kernel into the kernel cache (host only)."""
         _check(_lib().polar_build_kernel(self._h), "polar_build_kernel")
+
+    def layouts(self):
+        """The unrolled kernel's candidate layouts, the default first: dicts
+        of reg_stages, virtual_top and wave_lds_bytes."""
+        L = _lib()
+        out = []
+        for i in range(L.polar_layout_count(self._h)):
+            r, v, b = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+            _check(L.polar_layout_info(self._h, i, ctypes.byref(r), ctypes.byref(v), ctypes.byref(b)),
+                   "polar_layout_info")
+            out.append({"reg_stages": r.value, "virtual_top": v.value, "wave_lds_bytes": b.value})
+        return out
+
+    def set_layout(self, index):
+        _check(_lib().polar_set_layout(self._h, int(index)), "polar_set_layout")
+        self.layout = int(index)
+
+    def tune_layout(self, llr, out=None, stream=None):
+        """Time every layout on these frames and prepare the code with the
+        fastest (unrolled kernel, before prepare); returns its index."""
+        import torch
+        self._check_llr(llr)
+        if out is None:
+            out = torch.empty((llr.shape[0], self.row_bytes), dtype=torch.uint8, device=llr.device)
+        chosen = ctypes.c_int(-1)
+        _check(_lib().polar_tune_layout(self._h, ctypes.c_void_p(llr.data_ptr()), llr.shape[0],
+                                        ctypes.c_void_p(out.data_ptr()), _stream_handle(stream),
+                                        ctypes.byref(chosen)), "polar_tune_layout")
+        self.layout = chosen.value
+        self.prepared = True
+        return chosen.value
 
     def close(self):
         if getattr(self, "_h", None):

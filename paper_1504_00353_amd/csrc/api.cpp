@@ -72,6 +72,19 @@ polar_code* make_code(int n, std::vector<uint8_t>&& frozen) {
   return c;
 }
 
+// Releases what polar_prepare loaded, so the code can be configured and
+// prepared again.
+void unprepare(polar_code* c) {
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != c->device) (void)hipSetDevice(c->device);
+  if (c->d_ops) (void)hipFree(c->d_ops);
+  c->d_ops = nullptr;
+  polar::unrolled_unload(c->unrolled);
+  if (cur != c->device) (void)hipSetDevice(cur);
+  c->prepared = false;
+}
+
 }  // namespace
 
 polar_status polar_set_status(polar_status s) { return set(s); }
@@ -137,6 +150,46 @@ polar_status polar_set_fused_nodes(polar_code* c, int enable) {
   } catch (const std::bad_alloc&) {
     return set(POLAR_ENOMEM);
   }
+  return set(POLAR_OK);
+}
+
+int polar_layout_count(const polar_code* c) {
+  if (!c) {
+    set(POLAR_EINVAL);
+    return 0;
+  }
+  try {
+    const int n = (int)polar::unrolled_layouts(c->plan, c->llr_type).size();
+    set(POLAR_OK);
+    return n;
+  } catch (const std::bad_alloc&) {
+    set(POLAR_ENOMEM);
+    return 0;
+  }
+}
+
+polar_status polar_layout_info(const polar_code* c, int index, int* reg_stages, int* virtual_top,
+                               int* wave_lds_bytes) {
+  if (!c || index < 0) return set(POLAR_EINVAL);
+  try {
+    const std::vector<polar::UnrolledLayout> all = polar::unrolled_layouts(c->plan, c->llr_type);
+    if (index >= (int)all.size()) return set(POLAR_EINVAL);
+    const polar::UnrolledLayout& L = all[(size_t)index];
+    if (reg_stages) *reg_stages = L.nreg;
+    if (virtual_top) *virtual_top = L.vtop;
+    if (wave_lds_bytes)
+      *wave_lds_bytes = polar::wave_lds_bytes(c->plan.log2n, c->llr_type == POLAR_LLR_F32 ? 4 : 1, L.nreg + L.vtop);
+  } catch (const std::bad_alloc&) {
+    return set(POLAR_ENOMEM);
+  }
+  return set(POLAR_OK);
+}
+
+polar_status polar_set_layout(polar_code* c, int index) {
+  if (!c) return set(POLAR_EINVAL);
+  if (c->prepared) return set(POLAR_ESTATE);
+  if (index < 0 || index >= polar_layout_count(c)) return set(POLAR_EINVAL);
+  c->plan.layout = index;
   return set(POLAR_OK);
 }
 
@@ -324,6 +377,59 @@ polar_status polar_decode_trace(const polar_code* c, const void* llr, int nframe
   return decode_impl(c, llr, nframes, bits, trace, stream);
 }
 
+
+polar_status polar_tune_layout(polar_code* c, const void* llr, int nframes, uint8_t* bits, void* stream,
+                               int* chosen) {
+  if (!c || nframes < 1 || !llr || !bits) return set(POLAR_EINVAL);
+  if (c->prepared || c->kernel != POLAR_KERNEL_UNROLLED) return set(POLAR_ESTATE);
+  const int count = polar_layout_count(c);
+  if (count < 1) return set(POLAR_ENOMEM);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return set(POLAR_EDEVICE);
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return set(POLAR_EDEVICE);
+  }
+  int best = 0;
+  float best_ms = -1.0f;
+  polar_status st = POLAR_OK;
+  std::string msg;
+  for (int i = 0; i < count && st == POLAR_OK; ++i) {
+    c->plan.layout = i;
+    st = polar_prepare(c);
+    if (st != POLAR_OK) {
+      msg = g_message;
+      break;
+    }
+    float ms_min = -1.0f;
+    for (int rep = 0; rep < 4 && st == POLAR_OK; ++rep) {  // the first launch warms up
+      if (hipEventRecord(e0, (hipStream_t)stream) != hipSuccess ||
+          polar::unrolled_launch(c->unrolled, llr, nframes, bits, nullptr, c->waves_per_block, stream) != 0 ||
+          hipEventRecord(e1, (hipStream_t)stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        st = POLAR_EDEVICE;
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0 && (ms_min < 0.0f || ms < ms_min)) ms_min = ms;
+    }
+    unprepare(c);
+    if (st == POLAR_OK && (best_ms < 0.0f || ms_min < best_ms)) {
+      best_ms = ms_min;
+      best = i;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != POLAR_OK) {
+    c->plan.layout = 0;
+    return msg.empty() ? set(st) : set_msg(st, msg);
+  }
+  c->plan.layout = best;
+  st = polar_prepare(c);
+  if (st == POLAR_OK && chosen) *chosen = best;
+  return st;
+}
 
 /* ------------------------------------------------------------------ batch */
 

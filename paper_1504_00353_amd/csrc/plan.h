@@ -29,6 +29,7 @@ struct Plan {
   int k = 0;        // information bits
   int algo = 0;     // 0 Fast-SSC, 1 SC
   int fuse = 1;     // Fast-SSC: fuse leaf-pair nodes of size <= 64 (DOP_P01 .. DOP_REPR1)
+  int layout = 0;   // unrolled kernels: index into unrolled_layouts(), 0 = the default rule
   std::vector<uint8_t> frozen;          // N flags
   std::vector<int32_t> lkind, lsize, loff;  // logical schedule
   std::vector<uint32_t> dops;           // device schedule, one word per op, plus one padding op

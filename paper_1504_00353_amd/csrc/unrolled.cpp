@@ -95,37 +95,81 @@ bool write_file_atomic(const std::string& path, const std::vector<char>& data) {
 
 }  // namespace
 
-UnrolledLayout unrolled_layout(const Plan& p, int llr_type) {
+namespace {
+
+// The virtual top stage needs both children of the root to be inner nodes
+// (or Rate-0): no decision node of size N or N/2.
+bool vtop_allowed(const Plan& p) {
+  for (int i = 0; i < p.nops; ++i) {
+    const unsigned code = p.dops[i] & 0xffu, st = (p.dops[i] >> 8) & 0xffu;
+    if ((st == (unsigned)p.log2n || st == (unsigned)p.log2n - 1) && code >= DOP_R1 && code <= DOP_SPC) return false;
+  }
+  return true;
+}
+
+// The default rule: int8 keeps 2 (N = 32768, below a virtual top stage when
+// allowed) or 1 (N = 16384) stages in registers; float codes of N >= 16384
+// use the virtual top stage and one register stage when allowed.
+UnrolledLayout default_layout(const Plan& p, int llr_type) {
   UnrolledLayout L;
   if (llr_type != 0) {
-    // float: N >= 16384 drops its largest LDS stage (virtual top stage) when
-    // no decision node sits at the top two stages, and keeps the next one
-    // in registers
-    if (p.log2n >= 14) {
-      bool ok = true;
-      for (int i = 0; i < p.nops; ++i) {
-        const unsigned code = p.dops[i] & 0xffu, st = (p.dops[i] >> 8) & 0xffu;
-        if ((st == (unsigned)p.log2n || st == (unsigned)p.log2n - 1) && code >= DOP_R1 && code <= DOP_SPC) ok = false;
-      }
-      L.vtop = ok ? 1 : 0;
-      L.nreg = L.vtop;  // and the stage below it in registers
-    }
-    return L;
-  }
-  if (p.log2n == 15) {
+    if (p.log2n >= 14 && vtop_allowed(p)) L.vtop = L.nreg = 1;
+  } else if (p.log2n == 15) {
     L.nreg = 2;
-    // the virtual top stage needs both children of the root to be inner
-    // nodes (or Rate-0): no decision node of size N/2
-    bool ok = true;
-    for (int i = 0; i < p.nops; ++i) {
-      const unsigned code = p.dops[i] & 0xffu, st = (p.dops[i] >> 8) & 0xffu;
-      if ((st == 15 || st == 14) && code >= DOP_R1 && code <= DOP_SPC) ok = false;
-    }
-    L.vtop = ok ? 1 : 0;
+    L.vtop = vtop_allowed(p) ? 1 : 0;
   } else if (p.log2n == 14) {
     L.nreg = 1;
   }
   return L;
+}
+
+// What the decoder templates accept: int8 register stages of >= 2^11 LLRs,
+// at most 3 (a leaf at a register stage stages its bits in the highest LDS
+// stage), a virtual top stage only above a register stage and for N >= 8192;
+// float: one register stage below a virtual top stage (N >= 16384) or
+// neither.
+bool layout_valid(const Plan& p, int llr_type, UnrolledLayout L) {
+  if (L.vtop < 0 || L.vtop > 1 || L.nreg < 0) return false;
+  if (L.vtop && !vtop_allowed(p)) return false;
+  if (llr_type != 0) return (L.vtop == 0 && L.nreg == 0) || (L.vtop == 1 && L.nreg <= 1 && p.log2n >= 14);
+  if (L.nreg == 0) return L.vtop == 0;
+  return L.nreg <= 3 && p.log2n - L.vtop - L.nreg >= 11 && (L.vtop == 0 || p.log2n >= 13);
+}
+
+}  // namespace
+
+std::vector<UnrolledLayout> unrolled_layouts(const Plan& p, int llr_type) {
+  std::vector<UnrolledLayout> out;
+  out.push_back(default_layout(p, llr_type));
+  // {vtop, nreg}; int8 candidates keep their register stages within 64
+  // VGPRs (half the budget of four waves per SIMD), which rules out layouts
+  // that could only spill
+  static const int kTryI8[][2] = {{1, 2}, {1, 1}, {1, 3}, {0, 1}, {0, 2}, {0, 0}};
+  static const int kTryF32[][2] = {{1, 1}, {1, 0}, {0, 0}};
+  const int ntry = llr_type != 0 ? 3 : 6;
+  for (int i = 0; i < ntry && out.size() < 4; ++i) {
+    UnrolledLayout L;
+    L.vtop = llr_type != 0 ? kTryF32[i][0] : kTryI8[i][0];
+    L.nreg = llr_type != 0 ? kTryF32[i][1] : kTryI8[i][1];
+    if (!layout_valid(p, llr_type, L)) continue;
+    if (llr_type == 0) {
+      int regs = 0;
+      for (int t = p.log2n - 1 - L.vtop; t > p.log2n - 1 - L.vtop - L.nreg; --t) regs += (1 << t) >> 8;
+      if (regs > 64) continue;
+    }
+    bool dup = false;
+    for (const UnrolledLayout& o : out) dup = dup || (o.vtop == L.vtop && o.nreg == L.nreg);
+    if (!dup) out.push_back(L);
+  }
+  return out;
+}
+
+UnrolledLayout unrolled_layout(const Plan& p, int llr_type) {
+  if (p.layout > 0) {
+    const std::vector<UnrolledLayout> all = unrolled_layouts(p, llr_type);
+    if (p.layout < (int)all.size()) return all[(size_t)p.layout];
+  }
+  return default_layout(p, llr_type);
 }
 
 int unrolled_wave_bytes(const Plan& p, int llr_type) {

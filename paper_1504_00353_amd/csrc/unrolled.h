@@ -17,13 +17,18 @@ struct UnrolledKernel {
   int wave_bytes = 0;  // LDS slot of one wavefront
 };
 
-// How a generated int8 kernel places the widest alpha stages: nreg stages
-// in registers, and with vtop the stage below the root not stored at all.
+// How a generated kernel places the widest alpha stages: nreg stages in
+// registers, and with vtop the stage below the root not stored at all.
 struct UnrolledLayout {
   int nreg = 0;
   int vtop = 0;
 };
+// The layout the plan's kernel uses: candidate p.layout of
+// unrolled_layouts() (0, the default rule, when out of range).
 UnrolledLayout unrolled_layout(const Plan& p, int llr_type);
+// Every layout the decoder templates accept for this plan, the default rule
+// first; the autotuner times them.
+std::vector<UnrolledLayout> unrolled_layouts(const Plan& p, int llr_type);
 // LDS bytes of one wavefront of the generated kernel of this plan.
 int unrolled_wave_bytes(const Plan& p, int llr_type);
 

@@ -57,6 +57,14 @@ ALL = [SC_1024, FSSC_32K, FSSC_32K_F32, MIXED, SERVING, STRESS]
 
 # Further codes whose unrolled kernels are built ahead of time: the small
 # codes of the smoke run and of the unrolled-kernel parity tests.
+# codes whose unrolled kernels are built in every layout the autotuner
+# times (layout parity tests, polar_tune_layout)
+UNROLLED_LAYOUTS = [
+    (32768, 29492, 4.0, "fastssc", "i8"),
+    (4096, 3686, 4.0, "fastssc", "i8"),
+    (16384, 14746, 4.0, "fastssc", "f32"),
+]
+
 # unrolled kernels built with the fused leaf-pair nodes switched off (the
 # fused-vs-separate comparison)
 UNROLLED_UNFUSED = [

@@ -240,3 +240,38 @@ def test_set_fused_nodes_arguments():
     assert L.polar_set_fused_nodes(None, 1) == binding.EINVAL
     assert L.polar_device_schedule(None, None, 0, None) == binding.EINVAL
     assert L.polar_set_fused_nodes(c.handle, 0) == binding.OK
+
+
+def test_layout_candidates_and_arguments():
+    """Layouts of the unrolled kernels: index 0 is the default rule, every
+    candidate satisfies the decoder templates' constraints, and the LDS slot
+    follows from the register stages."""
+    L = binding.lib()
+    c = binding.Code(32768, 29492, 4.0, prepare=False, kernel="unrolled")
+    lay = c.layouts()
+    assert lay[0] == {"reg_stages": 2, "virtual_top": 1, "wave_lds_bytes": 8192}
+    assert len(lay) == len({(x["reg_stages"], x["virtual_top"]) for x in lay})
+    for x in lay:  # int8: register stages of >= 2^11 LLRs, at most 3
+        assert 1 <= x["reg_stages"] <= 3 and 15 - x["virtual_top"] - x["reg_stages"] >= 11
+    f = binding.Code(32768, 29492, 4.0, llr="f32", prepare=False, kernel="unrolled")
+    assert f.layouts()[0] == {"reg_stages": 1, "virtual_top": 1, "wave_lds_bytes": 36480}
+    assert all(x["reg_stages"] <= x["virtual_top"] for x in f.layouts())
+    s = binding.Code(1024, 512, 2.5, prepare=False, kernel="unrolled")
+    assert s.layouts() == [{"reg_stages": 0, "virtual_top": 0, "wave_lds_bytes": 1152}]
+    assert L.polar_layout_count(None) == 0
+    assert L.polar_set_layout(c.handle, -1) == binding.EINVAL
+    assert L.polar_set_layout(c.handle, len(lay)) == binding.EINVAL
+    assert L.polar_layout_info(c.handle, len(lay), None, None, None) == binding.EINVAL
+    assert L.polar_set_layout(c.handle, len(lay) - 1) == binding.OK
+    assert L.polar_tune_layout(c.handle, None, 1, None, None, None) == binding.EINVAL
+    sched = binding.Code(32768, 29492, 4.0, prepare=False, kernel="schedule")
+    assert L.polar_tune_layout(sched.handle, ctypes.c_void_p(16), 1, ctypes.c_void_p(16), None, None) == binding.ESTATE
+
+
+def test_virtual_top_only_without_top_decision_nodes():
+    """A code whose root child is a decision node cannot use the virtual top
+    stage: no candidate offers it."""
+    fr = np.zeros(16384, np.uint8)
+    fr[:8192] = 1  # left half Rate-0, right half Rate-1: decision node of size N/2
+    c = binding.Code(frozen=fr, prepare=False, kernel="unrolled")
+    assert all(x["virtual_top"] == 0 for x in c.layouts())

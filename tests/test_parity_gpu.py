@@ -331,3 +331,29 @@ def test_leaf_pair_mask_schedule_kernel(llr, fused):
     code = Code(frozen=fr, llr="f32" if llr == "f32" else "i8", fused=fused)
     rng = np.random.default_rng(77 + len(llr))
     check_parity(code, fr, random_llrs(rng, 200, n, llr), "fastssc", label="pairs %s %s" % (llr, fused))
+
+
+@pytest.mark.parametrize("spec", workloads.UNROLLED_LAYOUTS, ids=lambda t: "%d_%d_%s" % (t[0], t[1], t[4]))
+def test_every_layout_matches_oracle(spec):
+    """Each register/LDS layout the autotuner can pick decodes the same bits
+    and leaf LLRs as the oracle; the tuner leaves the code prepared with one
+    of them and decoding the same bits."""
+    n, k, d, algo, llr = spec
+    probe = Code(n, k, d, algo=algo, llr=llr, kernel="unrolled", prepare=False)
+    count = len(probe.layouts())
+    fr = probe.frozen()
+    _, _, l = make_frames(fr, 21, 64 if n >= 16384 else 200, d, llr)
+    rng = np.random.default_rng(n)
+    l = np.concatenate([l, random_llrs(rng, 8, n, "f32" if llr == "f32" else "i8")])
+    bits = []
+    for i in range(count):
+        code = Code(n, k, d, algo=algo, llr=llr, kernel="unrolled", layout=i)
+        check_parity(code, fr, l, algo, label="layout %d of %s" % (i, spec))
+        bits.append(gpu_decode(code, l)[0])
+        code.close()
+    tuned = Code(n, k, d, algo=algo, llr=llr, kernel="unrolled", prepare=False)
+    t = torch.from_numpy(np.ascontiguousarray(l)).cuda()
+    chosen = tuned.tune_layout(t)
+    assert 0 <= chosen < count
+    b, _ = gpu_decode(tuned, l)
+    assert np.array_equal(b, bits[0])
