@@ -125,7 +125,9 @@ polar_status polar_layout_info(const polar_code* code, int index, int* reg_stage
                                int* wave_lds_bytes);
 
 /* Selects layout `index` for the code's unrolled kernel (and for batches
- * created from the code afterwards).  Before polar_prepare.  Errors:
+ * created from the code afterwards).  Before polar_prepare; polar_configure
+ * and polar_set_fused_nodes reset it to 0, since the candidates depend on
+ * the LLR type and the schedule.  Errors:
  * POLAR_EINVAL (index out of range), POLAR_ESTATE (prepared). */
 polar_status polar_set_layout(polar_code* code, int index);
 

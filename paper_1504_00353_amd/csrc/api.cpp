@@ -133,6 +133,7 @@ polar_status polar_configure(polar_code* c, int algo, int llr_type) {
   try {
     c->plan.algo = algo;
     c->llr_type = llr_type;
+    c->plan.layout = 0;  // the candidates depend on the LLR type and the schedule
     polar::build_schedule(c->plan);
   } catch (const std::bad_alloc&) {
     return set(POLAR_ENOMEM);
@@ -146,6 +147,7 @@ polar_status polar_set_fused_nodes(polar_code* c, int enable) {
   if (enable != 0 && enable != 1) return set(POLAR_EINVAL);
   try {
     c->plan.fuse = enable;
+    c->plan.layout = 0;
     polar::build_schedule(c->plan);
   } catch (const std::bad_alloc&) {
     return set(POLAR_ENOMEM);

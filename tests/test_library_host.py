@@ -275,3 +275,15 @@ def test_virtual_top_only_without_top_decision_nodes():
     fr[:8192] = 1  # left half Rate-0, right half Rate-1: decision node of size N/2
     c = binding.Code(frozen=fr, prepare=False, kernel="unrolled")
     assert all(x["virtual_top"] == 0 for x in c.layouts())
+
+
+def test_configure_resets_layout():
+    """The layout index refers to the candidates of the configuration it was
+    chosen in; reconfiguring returns to the default."""
+    L = binding.lib()
+    c = binding.Code(32768, 29492, 4.0, prepare=False, kernel="unrolled", layout=3)
+    assert L.polar_configure(c.handle, 0, 1) == binding.OK  # float LLRs: 3 candidates
+    assert L.polar_layout_count(c.handle) == 3
+    assert L.polar_set_layout(c.handle, 2) == binding.OK
+    assert L.polar_set_fused_nodes(c.handle, 0) == binding.OK
+    assert L.polar_set_layout(c.handle, 3) == binding.EINVAL
