@@ -61,7 +61,7 @@ def speed(code, l, prewarm_s=0.25):
         code.decode(l)
         torch.cuda.synchronize()
     t = []
-    for _ in range(5):
+    for _ in range(25):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         code.decode(l)
