@@ -382,7 +382,7 @@ polar_status polar_decode_trace(const polar_code* c, const void* llr, int nframe
 
 polar_status polar_tune_layout(polar_code* c, const void* llr, int nframes, uint8_t* bits, void* stream,
                                int* chosen) {
-  if (!c || nframes < 1 || !llr || !bits) return set(POLAR_EINVAL);
+  if (!c || nframes < 1 || !llr || !bits || ((uintptr_t)llr & 3u) != 0) return set(POLAR_EINVAL);
   if (c->prepared || c->kernel != POLAR_KERNEL_UNROLLED) return set(POLAR_ESTATE);
   const int count = polar_layout_count(c);
   if (count < 1) return set(POLAR_ENOMEM);
