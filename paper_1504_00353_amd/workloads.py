@@ -65,6 +65,9 @@ UNROLLED_LAYOUTS = [
     (16384, 14746, 4.0, "fastssc", "f32"),
 ]
 
+# a batch whose codes use non-default layouts: (N, K, design dB, layout)
+BATCH_LAYOUTS = [(32768, 29492, 4.0, 2), (4096, 3686, 4.0, 1), (1024, 512, 2.5, 0)]
+
 # unrolled kernels built with the fused leaf-pair nodes switched off (the
 # fused-vs-separate comparison)
 UNROLLED_UNFUSED = [

@@ -153,3 +153,17 @@ def test_batch_zero_frames(mixed):
     batch.decode(llr, bits)
     torch.cuda.synchronize()
     assert int(bits.sum()) == 0
+
+
+def test_batch_of_codes_with_layouts():
+    """Codes prepared with non-default register/LDS layouts carry them into
+    a batch: every frame still equals the oracle."""
+    codes = [Code(n, k, d, llr="i8", prepare=False, layout=lay) for n, k, d, lay in workloads.BATCH_LAYOUTS]
+    batch = Batch(codes)
+    frozens = [c.frozen() for c in codes]
+    code_idx, offs, flat, _ = make_mixed(frozens, 77, 300, (3.0, 5.0))
+    rows, _, _ = run(batch, codes, code_idx, offs, flat)
+    exp = expected_rows(frozens, code_idx, flat, offs)
+    bad = [i for i in range(len(rows)) if not np.array_equal(rows[i], exp[i])]
+    assert not bad, "%d frames differ, first %s" % (len(bad), bad[:5])
+    batch.close()
