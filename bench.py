@@ -7,7 +7,8 @@ Gb/s single-core figure for this code.  Prints one JSON line:
 
   value        information throughput (Gb/s) of the batched decode;
   latency_us   p50/p99 frame latency of a batched launch (submit -> done);
-  plain        the same frames decoded with one launch per frame;
+  plain        the same frames decoded with one launch per frame (and with
+               the layout the autotuner picks for one frame per launch);
   roofline     algorithmic HBM bytes (LLR in + info bits out) per launch
                over the decode kernel's mean duration vs 8 TB/s (and vs a
                measured plain copy of 1 GiB);
@@ -417,6 +418,24 @@ def main():
         plain = {"value": round(plain_gbps, 4), "unit": "Gbps", "frames": pf,
                  "latency_us": {"p50": round(percentile(plat, 50), 2), "p99": round(percentile(plat, 99), 2)},
                  "bits_equal_batched": True}
+        if args.kernel == "unrolled":
+            # the same single-frame launches with the register/LDS layout the
+            # autotuner picks for one frame per launch (latency, not occupancy)
+            lc = Code(n, k, design, algo="fastssc", llr="i8", kernel="unrolled", prepare=False)
+            chosen = lc.tune_layout(llr[:1])
+            tl = []
+            for i in range(min(pf, 100)):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                lc.decode(llr[i:i + 1], out=outs1[i:i + 1])
+                torch.cuda.synchronize()
+                tl.append((time.perf_counter() - t) * 1e6)
+            assert torch.equal(outs1[:min(pf, 100)], out[:min(pf, 100)]), "latency-tuned decode differs"
+            plain["latency_tuned"] = {"layout": dict(lc.layouts()[chosen], index=chosen),
+                                      "latency_us": {"p50": round(percentile(tl, 50), 2),
+                                                     "p99": round(percentile(tl, 99), 2)},
+                                      "what": "one frame per launch, layout tuned on one frame"}
+            lc.close()
 
     # host-inclusive: LLRs from pinned host memory, bits back to it (PCIe), per step
     host = None
