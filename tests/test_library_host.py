@@ -264,6 +264,8 @@ def test_layout_candidates_and_arguments():
     assert L.polar_layout_info(c.handle, len(lay), None, None, None) == binding.EINVAL
     assert L.polar_set_layout(c.handle, len(lay) - 1) == binding.OK
     assert L.polar_tune_layout(c.handle, None, 1, None, None, None) == binding.EINVAL
+    assert L.polar_tune_layout(c.handle, ctypes.c_void_p(18), 1, ctypes.c_void_p(16), None, None) == binding.EINVAL
+    assert L.polar_tune_layout(c.handle, ctypes.c_void_p(16), 0, ctypes.c_void_p(16), None, None) == binding.EINVAL
     sched = binding.Code(32768, 29492, 4.0, prepare=False, kernel="schedule")
     assert L.polar_tune_layout(sched.handle, ctypes.c_void_p(16), 1, ctypes.c_void_p(16), None, None) == binding.ESTATE
 
