@@ -116,6 +116,22 @@ __device__ __forceinline__ uint64_t transform64(uint64_t x, int size) {
   return x;
 }
 
+// transform64 of a node of at most 32 bits, in 32-bit scalar operations
+template <int NV>
+__device__ __forceinline__ uint64_t transform_node(uint64_t x) {
+  if constexpr (NV <= 32) {
+    uint32_t y = (uint32_t)x;
+    if constexpr (NV > 1) y ^= (y >> 1) & 0x55555555u;
+    if constexpr (NV > 2) y ^= (y >> 2) & 0x33333333u;
+    if constexpr (NV > 4) y ^= (y >> 4) & 0x0F0F0F0Fu;
+    if constexpr (NV > 8) y ^= (y >> 8) & 0x00FF00FFu;
+    if constexpr (NV > 16) y ^= (y >> 16) & 0x0000FFFFu;
+    return (uint64_t)y;
+  } else {
+    return transform64(x, NV);
+  }
+}
+
 __device__ __forceinline__ uint32_t transform32(uint32_t x) {
   x ^= (x >> 1) & 0x55555555u;
   x ^= (x >> 2) & 0x33333333u;
@@ -300,7 +316,7 @@ struct Dec {
     uint64_t hd = ballot(x < 0.0f) & m;
     if (code == DOP_R1) {
       set_win(off, m, hd);
-      pend_v = transform64(hd, NV);
+      pend_v = transform_node<NV>(hd);
       pend_n = NV;
     } else if (code == DOP_REP) {
       float s = x;
@@ -328,7 +344,7 @@ struct Dec {
         hd ^= 1ull << (__ffsll((unsigned long long)cand) - 1);
       }
       set_win(off, m, hd);
-      pend_v = transform64(hd, NV) >> 1;
+      pend_v = transform_node<NV>(hd) >> 1;
       pend_n = NV - 1;
     }
   }
@@ -380,10 +396,10 @@ struct Dec {
         const uint64_t cand = ballot(lane < H && fabsf(g) == mn);
         hd ^= 1ull << (__ffsll((unsigned long long)cand) - 1);
       }
-      out = transform64(hd, H) >> 1;
+      out = transform_node<H>(hd) >> 1;
       nout = H - 1;
     } else {
-      out = transform64(hd, H);
+      out = transform_node<H>(hd);
       nout = H;
     }
     set_win(off, low_mask(NV), (((rep ? m : 0ull) ^ hd) | (hd << H)));
