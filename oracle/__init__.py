@@ -48,6 +48,7 @@ def lib():
         L.oracle_construct.argtypes = [I, I, ctypes.c_double, P]
         L.oracle_encode.argtypes = [I, I, P, P]
         L.oracle_bhattacharyya.argtypes = [I, ctypes.c_double, P]
+        L.oracle_construct_lnz.argtypes = [I, I, ctypes.c_double, P, P]
         for name in ("oracle_decode_i8", "oracle_decode_f32", "oracle_decode_f64"):
             getattr(L, name).argtypes = [I, P, I, I, P, P, P, P, I]
         L.oracle_schedule.argtypes = [I, P, I, P, P, I]
@@ -74,6 +75,16 @@ def construct(n, k, design_ebn0_db):
     if rc:
         raise ValueError("oracle_construct(%d, %d) failed" % (n, k))
     return frozen
+
+
+def construct_reliability(n, k, design_ebn0_db):
+    """(ln z of every bit channel, ln z0 of the channel) that construct()
+    ranks for an (n, k) code at the design Eb/N0."""
+    out = np.zeros(n, np.float64)
+    z0 = np.zeros(1, np.float64)
+    if lib().oracle_construct_lnz(n, k, float(design_ebn0_db), _ptr(out), _ptr(z0)):
+        raise ValueError("oracle_construct_lnz(%d, %d) failed" % (n, k))
+    return out, float(z0[0])
 
 
 def bhattacharyya(n, lnz0):

@@ -294,12 +294,22 @@ int oracle_bhattacharyya(int n, double lnz0, double* lnz) {
   return 0;
 }
 
-int oracle_construct(int n, int k, double design_ebn0_db, uint8_t* frozen) {
-  if (!is_pow2(n) || n < 2 || k < 0 || k > n || !frozen) return 1;
+// ln z of every bit channel of an (n, k) code designed at Eb/N0 = design_ebn0_db
+// (the reliabilities oracle_construct ranks): BPSK over AWGN at the design
+// point has Es/N0 = R Eb/N0 with R = k/n, and its Bhattacharyya parameter is
+// z0 = exp(-Es/N0).  *lnz0 (may be null) receives ln z0.  Returns 0 on success.
+int oracle_construct_lnz(int n, int k, double design_ebn0_db, double* lnz, double* lnz0) {
+  if (!is_pow2(n) || n < 2 || k < 0 || k > n || !lnz) return 1;
   double rate = (double)k / (double)n;
   double es_n0 = rate * std::pow(10.0, design_ebn0_db / 10.0);
+  if (lnz0) *lnz0 = -es_n0;
+  return oracle_bhattacharyya(n, -es_n0, lnz);
+}
+
+int oracle_construct(int n, int k, double design_ebn0_db, uint8_t* frozen) {
+  if (!is_pow2(n) || n < 2 || k < 0 || k > n || !frozen) return 1;
   std::vector<double> lnz(n);
-  oracle_bhattacharyya(n, -es_n0, lnz.data());
+  oracle_construct_lnz(n, k, design_ebn0_db, lnz.data(), nullptr);
   // Rank: most reliable (smallest ln z) first; equal values -> higher index first.
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;

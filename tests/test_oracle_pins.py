@@ -173,7 +173,7 @@ def test_node_decoder_is_ml(kind, n, dtype):
     rng = np.random.default_rng(1000 * n + len(kind))
     for trial in range(300):
         if dtype == "i8":
-            alpha = rng.integers(-127, 128, size=n).astype(np.int8)
+            alpha = rng.integers(-128, 128, size=n).astype(np.int8)
             if trial % 3 == 0:   # many ties and zeros
                 alpha = rng.integers(-2, 3, size=n).astype(np.int8)
             metric = sign @ alpha.astype(np.int64)
@@ -358,3 +358,84 @@ def test_construction_invariants(n, k, d):
         lo = idx[(idx & h) == 0]
         assert not (frozen[lo + h] & (frozen[lo] == 0)).any()
         h *= 2
+
+
+# ------------------------------------------- construction channel parameter
+
+def awgn_bhattacharyya_numeric(rate, ebn0_db):
+    """Bhattacharyya parameter of BPSK (0 -> +1, 1 -> -1) over AWGN at the
+    given Eb/N0, from its definition: the integral over y of
+    sqrt(p(y | +1) p(y | -1)), with noise variance 1 / (2 R Eb/N0),
+    integrated numerically."""
+    from scipy import integrate
+    sigma2 = 1.0 / (2.0 * rate * 10.0 ** (ebn0_db / 10.0))
+
+    def density(y, s):
+        return np.exp(-(y - s) ** 2 / (2 * sigma2)) / np.sqrt(2 * np.pi * sigma2)
+
+    z, err = integrate.quad(lambda y: np.sqrt(density(y, 1.0) * density(y, -1.0)), -np.inf, np.inf,
+                            epsabs=0, epsrel=1e-12, limit=200)
+    assert err < 1e-10 * z
+    return z
+
+
+@pytest.mark.parametrize("n,k,d", [(1024, 512, 2.5), (32768, 29492, 4.0), (4096, 3686, 4.0),
+                                   (256, 128, 2.5), (1024, 850, 4.0), (64, 16, 0.0), (16384, 15565, 6.0)])
+def test_design_channel_is_bpsk_awgn_bhattacharyya(n, k, d):
+    """Sec. II-A construction: the channel the oracle starts its reliability
+    recursion from is the Bhattacharyya parameter of BPSK over AWGN at the
+    design Eb/N0 of a rate-K/N code (checked against the numerically
+    integrated definition, not a closed form), and the frozen set is the
+    N - K channels of largest ln z, ties frozen at the lower index."""
+    lnz, lnz0 = oracle.construct_reliability(n, k, d)
+    assert lnz0 == pytest.approx(np.log(awgn_bhattacharyya_numeric(k / n, d)), rel=1e-9, abs=0)
+    assert np.array_equal(lnz, oracle.bhattacharyya(n, lnz0))
+    order = sorted(range(n), key=lambda i: (lnz[i], -i))  # most reliable first, higher index first on ties
+    expect = np.ones(n, np.uint8)
+    expect[order[:k]] = 0
+    assert np.array_equal(oracle.construct(n, k, d), expect)
+
+
+def test_fastssc_tree_sizes_match_independent_count():
+    """The oracle's Fast-SSC schedule of the benchmark codes has the sizes
+    counted independently of it (tests/golden/fastssc_sizes.txt): number of
+    node functions, leaves of each kind and the elements they cover, f and
+    G_0R elements.  Pins construction, node classification and pruning at
+    full size together."""
+    import collections
+    rows = read_golden("fastssc_sizes.txt")
+    assert rows
+    for row in rows:
+        n, k, d = int(row[0]), int(row[1]), float(row[2])
+        sched = oracle.schedule(oracle.construct(n, k, d), "fastssc")
+        count = collections.Counter(name for name, _ in sched)
+        elems = collections.Counter()
+        for name, size in sched:
+            elems[name] += size // 2 if name in ("F", "G", "G_0R", "Combine", "Combine_0R") else size
+        got = [len(sched), count["Info"], count["Repetition"], count["SPC"],
+               elems["Info"], elems["Repetition"], elems["SPC"], elems["F"], elems["G_0R"]]
+        for want, have in zip(row[3:], got):
+            if want != "-":
+                assert int(want) == have, (n, k, row, got)
+
+
+@pytest.mark.parametrize("n,k,d,algo", [(64, 32, 2.5, "fastssc"), (64, 32, 2.5, "sc"),
+                                        (1024, 512, 2.5, "fastssc"), (1024, 512, 2.5, "sc"),
+                                        (4096, 3686, 4.0, "fastssc")])
+def test_channel_minus128_is_read_as_minus127(n, k, d, algo):
+    """Listing 4 keeps 8-bit LLRs in the symmetric range [-127, 127]; a
+    channel value of -128 (representable in int8) is read as -127: decoding a
+    frame that contains -128 gives the bits and leaf LLRs of the same frame
+    with -127 in its place."""
+    frozen = oracle.construct(n, k, d)
+    rng = np.random.default_rng(n + k + len(algo))
+    llr = rng.integers(-128, 128, size=(24, n)).astype(np.int8)
+    llr[:8] = np.where(rng.random((8, n)) < 0.3, np.int8(-128), llr[:8])   # dense -128
+    llr[8:16] = rng.choice(np.array([-128, -127, 127, 1, -1, 0], np.int8), size=(8, n))
+    assert (llr == -128).any()
+    u, x, t = oracle.decode(frozen, llr, algo, trace=True)
+    u2, x2, t2 = oracle.decode(frozen, np.maximum(llr, np.int8(-127)), algo, trace=True)
+    assert np.array_equal(u, u2)
+    assert np.array_equal(x, x2)
+    assert np.array_equal(t, t2)
+    assert t.min() >= -127
