@@ -91,9 +91,11 @@ polar_code* polar_construct(int n, int k, double design_ebn0_db);
  * K = N - sum(frozen) must be >= 1.  The mask is copied. */
 polar_code* polar_construct_mask(int n, const uint8_t* frozen);
 
-/* Selects the algorithm (polar_algo) and LLR type (polar_llr).  Must be
- * called before polar_prepare(); POLAR_ESTATE afterwards. */
-polar_status polar_configure(polar_code* code, int algo, int llr_type);
+/* Selects the algorithm (Fast-SSC, Sec. II-E, or plain SC, Sec. II-B) and
+ * the LLR type (8-bit fixed point, Sec. III-A.1, or binary32).  Must be
+ * called before polar_prepare(); POLAR_ESTATE afterwards, POLAR_EINVAL for
+ * a value outside the enums. */
+polar_status polar_configure(polar_code* code, polar_algo algo, polar_llr llr_type);
 
 /* Fast-SSC only: enable (1, the default) or disable (0) the fused nodes of
  * the Fast-SSC function library (Sec. II-E): every internal node of size
@@ -107,8 +109,9 @@ polar_status polar_configure(polar_code* code, int algo, int llr_type);
 polar_status polar_set_fused_nodes(polar_code* code, int enable);
 
 /* Selects the kernel (polar_kernel); default POLAR_KERNEL_SCHEDULE.  Must
- * be called before polar_prepare(); POLAR_ESTATE afterwards. */
-polar_status polar_set_kernel(polar_code* code, int kernel);
+ * be called before polar_prepare(); POLAR_ESTATE afterwards, POLAR_EINVAL
+ * for a value outside the enum. */
+polar_status polar_set_kernel(polar_code* code, polar_kernel kernel);
 
 /* Layouts of an unrolled kernel's widest alpha stages (how many stages sit
  * in registers instead of LDS, and whether the stage below the root is
@@ -208,19 +211,28 @@ polar_status polar_device_schedule(const polar_code* code, uint32_t* ops, int ca
 polar_status polar_encode(const polar_code* code, const uint8_t* info, int nframes, uint8_t* x);
 
 /* Decodes nframes frames on the given HIP stream (hipStream_t, NULL = the
- * default stream).  Asynchronous: never allocates, frees or synchronises,
- * so it can be captured in a HIP graph.
+ * default stream): for each frame, the successive-cancellation walk of the
+ * decoder tree (Sec. II-B, II-C: f of eq. (1) to the left child, g of
+ * eq. (2) to the right child, the combine of eq. (3)), pruned at Rate-0 and
+ * Rate-1 nodes (Sec. II-D) and, for Fast-SSC, at repetition and SPC nodes
+ * (Sec. II-E), in the order of Listing 1.  The output is the information
+ * part of u_hat = x_hat G_N (Sec. II-A).  Asynchronous: never allocates,
+ * frees or synchronises, so it can be captured in a HIP graph.
  *   llr : device memory, [nframes][N] of int8 or float (as configured),
- *         natural index order.  int8 -128 is read as -127.
+ *         natural index order.  int8 follows Listing 4's symmetric range:
+ *         -128 is read as -127.  int8 rows must start on a 4-byte boundary
+ *         (16 recommended), float rows on a 16-byte boundary (the kernels
+ *         read 128-bit words).
  *   bits: device memory, [nframes][ceil(K/8)] bytes: u_hat over the
  *         information set in increasing index order, LSB first, pad bits 0.
  * Both buffers belong to the caller and must stay alive until the stream
- * has run the decode.  llr must be 4-byte aligned (16 recommended).
+ * has run the decode; their contents must be ready in stream order.
  * nframes == 0 is a no-op.  Errors: POLAR_EINVAL (NULL buffers with
  * nframes > 0, nframes < 0, misaligned llr), POLAR_ESTATE (not prepared,
  * or the current device is not the one the code was prepared on),
- * POLAR_EDEVICE (launch failed).  Kernel faults surface at the caller's
- * next synchronisation. */
+ * POLAR_EDEVICE (the launch itself failed; an error left on the thread by
+ * an earlier call is not reported).  Kernel faults surface at the
+ * caller's next synchronisation. */
 polar_status polar_decode(const polar_code* code, const void* llr, int nframes, uint8_t* bits,
                           void* stream);
 
@@ -275,8 +287,8 @@ polar_status polar_batch_set_frames(polar_batch* batch, int nframes, const int32
 /* Decodes the frames of the last polar_batch_set_frames() in one launch on
  * the given stream.  Asynchronous; never allocates or synchronises, so it
  * can be captured in a HIP graph (the descriptors must not change between
- * capture and replay).  llr: device memory of the batch's LLR type, 4-byte
- * aligned; bits: device memory.  Errors: POLAR_EINVAL, POLAR_ESTATE (not
+ * capture and replay).  llr: device memory of the batch's LLR type, aligned
+ * as for polar_decode (4 bytes int8, 16 bytes float); bits: device memory.  Errors: POLAR_EINVAL, POLAR_ESTATE (not
  * prepared, or the current device is not the batch's), POLAR_EDEVICE. */
 polar_status polar_batch_decode(const polar_batch* batch, const void* llr, uint8_t* bits, void* stream);
 
@@ -304,9 +316,13 @@ void polar_batch_destroy(polar_batch* batch);
 
 /* ------------------------------------------------------------------------
  * Request server: continuous batching of decode requests over a prepared
- * batch.  A request is 1..n frames of one of the batch's codes, LLRs and
- * results in host memory.  Requests are admitted first come, first served
- * as soon as device slots for all their frames are free; every poll
+ * batch.  A request is 1..n frames of one of the batch's codes; its LLRs
+ * and its results each live in host or in device memory.  Requests are
+ * admitted first come, first served as soon as the device memory they need
+ * is free: LLR slots of the server's pool for host LLRs, bits slots for
+ * host results, and for buffers already in device memory a share of a
+ * byte budget of caller memory that admitted, unfinished requests may
+ * reference (the bytes the request pins on the device).  Every poll
  * retires finished steps (in whatever order they finish), admits what fits
  * and launches steps (batch decodes) over the admitted frames not yet
  * launched while server streams are free: one step per frame length, the
@@ -323,16 +339,20 @@ typedef struct polar_server polar_server; /* opaque; owned by the library */
 
 /* Creates a server on the current device for a prepared batch; codes /
  * ncodes must be the codes the batch was created from, in the same order.
- * slots_per_class: device frame slots for each distinct frame length N
- * (device memory: slots x (N x LLR size + ceil(K/8)) per length);
- * streams: steps in flight at once (1..8); staging_bytes: pinned host
- * memory holding submitted LLRs until their step has copied them.
- * Allocates device and pinned host memory.  NULL on error (see
+ * slots_per_class (>= 0): frame slots for each distinct frame length N in
+ * the server's LLR pool and in its bits pool, used by requests whose LLRs
+ * or results are in host memory (device memory: slots x (N x LLR size +
+ * ceil(K/8)) per length); device_bytes: the budget of caller device
+ * memory (LLR and result bytes) that admitted, unfinished requests with
+ * device-resident buffers may reference; at least one of the two must be
+ * non-zero.  streams: steps in flight at once (1..8); staging_bytes:
+ * pinned host memory holding submitted LLRs until their step has copied
+ * them.  Allocates device and pinned host memory.  NULL on error (see
  * polar_last_status: POLAR_EINVAL, POLAR_ESTATE if the batch is not
  * prepared or was prepared on another device, POLAR_ENOMEM,
  * POLAR_EDEVICE). */
 polar_server* polar_server_create(const polar_batch* batch, const polar_code* const* codes, int ncodes,
-                                  int slots_per_class, int streams, size_t staging_bytes);
+                                  int slots_per_class, int streams, size_t staging_bytes, size_t device_bytes);
 
 /* Where the buffers of a request live (flags for polar_server_submit). */
 enum { POLAR_SERVER_LLR_DEVICE = 1, POLAR_SERVER_BITS_DEVICE = 2 };
@@ -346,8 +366,13 @@ enum { POLAR_SERVER_LLR_DEVICE = 1, POLAR_SERVER_BITS_DEVICE = 2 };
  * the poll that reports the request done) or, with
  * POLAR_SERVER_BITS_DEVICE, in device memory (written in place by the
  * decode).  Buffers must stay valid until the request is reported done.
+ * Readiness: the server's streams do not wait for any other stream, so
+ * device buffers must be ready when submit is called -- the LLRs written
+ * and any earlier work on the result buffer finished (synchronise the
+ * stream that produced them first).
  * *id receives the request id (> 0).  Errors: POLAR_EINVAL (bad arguments,
- * or more frames than the code's length class has slots), POLAR_EAGAIN
+ * or a request that could never be admitted: more frames than its length
+ * class has slots, or more device bytes than the budget), POLAR_EAGAIN
  * (staging memory full: poll, then submit again), POLAR_EDEVICE (the
  * server has failed). */
 polar_status polar_server_submit(polar_server* server, int code_index, int nframes, const void* llr, int where,
@@ -372,7 +397,11 @@ polar_status polar_server_run_trace(polar_server* server, int nreq, const double
  * is current), POLAR_EDEVICE. */
 polar_status polar_server_poll(polar_server* server, int64_t* done_ids, int cap, int* ndone);
 
-/* Requests waiting for slots, admitted but not launched, and steps in
+/* Device bytes of caller memory referenced by admitted, unfinished
+ * requests, and the budget (any pointer may be NULL). */
+polar_status polar_server_device_bytes(const polar_server* server, size_t* in_use, size_t* budget);
+
+/* Requests waiting for memory, admitted but not launched, and steps in
  * flight (any pointer may be NULL). */
 polar_status polar_server_pending(const polar_server* server, int* waiting, int* admitted, int* inflight_steps);
 

@@ -28,6 +28,7 @@ EXPORTS = [
     "polar_batch_set_frames", "polar_batch_decode", "polar_batch_decode_desc", "polar_batch_tune",
     "polar_batch_launch_shape", "polar_batch_destroy", "polar_server_create", "polar_server_submit",
     "polar_server_poll", "polar_server_pending", "polar_server_destroy", "polar_server_run_trace",
+    "polar_server_device_bytes",
 ]
 
 
@@ -89,11 +90,12 @@ def _lib():
         L.polar_batch_launch_shape.argtypes = [P, P, P, P]
         L.polar_batch_destroy.argtypes = [P]
         L.polar_batch_destroy.restype = None
-        L.polar_server_create.argtypes = [P, P, I, I, I, ctypes.c_size_t]
+        L.polar_server_create.argtypes = [P, P, I, I, I, ctypes.c_size_t, ctypes.c_size_t]
         L.polar_server_create.restype = P
         L.polar_server_submit.argtypes = [P, I, I, P, I, P, P]
         L.polar_server_poll.argtypes = [P, P, I, P]
         L.polar_server_pending.argtypes = [P, P, P, P]
+        L.polar_server_device_bytes.argtypes = [P, P, P]
         L.polar_server_destroy.argtypes = [P]
         L.polar_server_destroy.restype = None
         L.polar_server_run_trace.argtypes = [P, I, P, P, P, P, P, P]
@@ -343,12 +345,13 @@ class Server:
     """Continuous-batching request server over a prepared Batch; see
     polar_server_* in include/polar.h.  One thread drives it."""
 
-    def __init__(self, batch, slots_per_class=4096, streams=2, staging_bytes=256 << 20):
+    def __init__(self, batch, slots_per_class=4096, streams=2, staging_bytes=256 << 20, device_bytes=1 << 30):
         L = _lib()
         self.batch = batch
         codes = batch.codes
         arr = (ctypes.c_void_p * len(codes))(*[c.handle.value for c in codes])
-        h = L.polar_server_create(batch._h, arr, len(codes), int(slots_per_class), int(streams), int(staging_bytes))
+        h = L.polar_server_create(batch._h, arr, len(codes), int(slots_per_class), int(streams), int(staging_bytes),
+                                  int(device_bytes))
         if not h:
             raise PolarError(L.polar_last_status(), "polar_server_create")
         self._h = ctypes.c_void_p(h)
@@ -363,6 +366,11 @@ class Server:
         (poll and retry)."""
         rid = ctypes.c_int64(0)
         where = 0
+        if hasattr(llr, "data_ptr") or hasattr(bits, "data_ptr"):
+            # the server's streams wait for no other stream: device buffers
+            # must be ready at submit (include/polar.h, polar_server_submit)
+            import torch
+            torch.cuda.current_stream().synchronize()
         if hasattr(llr, "data_ptr"):
             ptr, frames = llr.data_ptr(), llr.shape[0]
             where |= 1
@@ -405,6 +413,14 @@ class Server:
         _check(_lib().polar_server_run_trace(self._h, a.shape[0], _np_ptr(a), _np_ptr(c), _np_ptr(f), _np_ptr(lp),
                                              _np_ptr(bp), _np_ptr(done)), "polar_server_run_trace")
         return done
+
+    def device_bytes(self):
+        """(caller device bytes referenced by admitted, unfinished requests,
+        the budget)."""
+        used, budget = ctypes.c_size_t(0), ctypes.c_size_t(0)
+        _check(_lib().polar_server_device_bytes(self._h, ctypes.byref(used), ctypes.byref(budget)),
+               "polar_server_device_bytes")
+        return used.value, budget.value
 
     def pending(self):
         w, a, f = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)

@@ -14,7 +14,7 @@
 namespace polar {
 int launch_decode(const uint32_t* ops, int nops, int log2n, int kbits, int llr_type, const void* llr, int nframes,
                   uint8_t* bits, void* trace, int waves_per_block, void* stream);
-int set_lds_limit(int llr_type, int bytes);
+int set_lds_limit(int bytes);
 }  // namespace polar
 
 namespace {
@@ -39,6 +39,12 @@ polar_status set_msg(polar_status s, const std::string& msg) {
 bool on_device(int dev) {
   int cur = -1;
   return hipGetDevice(&cur) == hipSuccess && cur == dev;
+}
+
+// LLR buffers: int8 rows on 4-byte boundaries, float rows on 16-byte
+// boundaries (the kernels read whole 32-bit and 128-bit words).
+bool llr_aligned(int llr_type, const void* p) {
+  return ((uintptr_t)p & (llr_type == POLAR_LLR_F32 ? 15u : 3u)) == 0;
 }
 
 int log2_exact(int n) {
@@ -125,7 +131,7 @@ polar_code* polar_construct_mask(int n, const uint8_t* frozen) {
   return make_code(n, std::move(f));
 }
 
-polar_status polar_configure(polar_code* c, int algo, int llr_type) {
+polar_status polar_configure(polar_code* c, polar_algo algo, polar_llr llr_type) {
   if (!c) return set(POLAR_EINVAL);
   if (c->prepared) return set(POLAR_ESTATE);
   if ((algo != POLAR_ALGO_FASTSSC && algo != POLAR_ALGO_SC) || (llr_type != POLAR_LLR_I8 && llr_type != POLAR_LLR_F32))
@@ -195,7 +201,7 @@ polar_status polar_set_layout(polar_code* c, int index) {
   return set(POLAR_OK);
 }
 
-polar_status polar_set_kernel(polar_code* c, int kernel) {
+polar_status polar_set_kernel(polar_code* c, polar_kernel kernel) {
   if (!c) return set(POLAR_EINVAL);
   if (c->prepared) return set(POLAR_ESTATE);
   if (kernel != POLAR_KERNEL_SCHEDULE && kernel != POLAR_KERNEL_UNROLLED) return set(POLAR_EINVAL);
@@ -241,7 +247,7 @@ polar_status polar_prepare(polar_code* c) {
       return set(POLAR_ENOMEM);
     }
   } else {
-    if (polar::set_lds_limit(c->llr_type, wpb * wave_bytes) != hipSuccess) return set(POLAR_EDEVICE);
+    if (polar::set_lds_limit(lds_max) != hipSuccess) return set(POLAR_EDEVICE);
     const size_t bytes = c->plan.dops.size() * sizeof(uint32_t);
     uint32_t* d = nullptr;
     if (hipMalloc((void**)&d, bytes ? bytes : 4) != hipSuccess) return set(POLAR_ENOMEM);
@@ -310,10 +316,10 @@ polar_status polar_schedule(const polar_code* c, int32_t* kinds, int32_t* sizes,
   return set(POLAR_OK);
 }
 
-static_assert(POLAR_DOP_F == polar::DOP_F && POLAR_DOP_G_0R == polar::DOP_G0R &&
-                  POLAR_DOP_COMBINE_R0 == polar::DOP_CR0 && POLAR_DOP_SPC == polar::DOP_SPC &&
-                  POLAR_DOP_FLUSH == polar::DOP_FLUSH && POLAR_DOP_P01 == polar::DOP_P01 &&
-                  POLAR_DOP_REPR1 == polar::DOP_REPR1,
+static_assert((int)POLAR_DOP_F == (int)polar::DOP_F && (int)POLAR_DOP_G_0R == (int)polar::DOP_G0R &&
+                  (int)POLAR_DOP_COMBINE_R0 == (int)polar::DOP_CR0 && (int)POLAR_DOP_SPC == (int)polar::DOP_SPC &&
+                  (int)POLAR_DOP_FLUSH == (int)polar::DOP_FLUSH && (int)POLAR_DOP_P01 == (int)polar::DOP_P01 &&
+                  (int)POLAR_DOP_REPR1 == (int)polar::DOP_REPR1,
               "public device-op codes follow the kernels' codes");
 
 polar_status polar_device_schedule(const polar_code* c, uint32_t* ops, int cap, int* n_ops) {
@@ -359,7 +365,7 @@ static polar_status decode_impl(const polar_code* c, const void* llr, int nframe
   if (!c->prepared) return set(POLAR_ESTATE);
   if (nframes == 0) return set(POLAR_OK);
   if (!llr || !bits) return set(POLAR_EINVAL);
-  if (((uintptr_t)llr & 3u) != 0) return set(POLAR_EINVAL);
+  if (!llr_aligned(c->llr_type, llr)) return set(POLAR_EINVAL);
   if (c->llr_type == POLAR_LLR_F32 && trace && ((uintptr_t)trace & 3u) != 0) return set(POLAR_EINVAL);
   if (!on_device(c->device)) return set_msg(POLAR_ESTATE, "the current device is not the one the code was prepared on");
   const int rc = c->kernel == POLAR_KERNEL_UNROLLED
@@ -382,7 +388,7 @@ polar_status polar_decode_trace(const polar_code* c, const void* llr, int nframe
 
 polar_status polar_tune_layout(polar_code* c, const void* llr, int nframes, uint8_t* bits, void* stream,
                                int* chosen) {
-  if (!c || nframes < 1 || !llr || !bits || ((uintptr_t)llr & 3u) != 0) return set(POLAR_EINVAL);
+  if (!c || nframes < 1 || !llr || !bits || !llr_aligned(c->llr_type, llr)) return set(POLAR_EINVAL);
   if (c->prepared || c->kernel != POLAR_KERNEL_UNROLLED) return set(POLAR_ESTATE);
   const int count = polar_layout_count(c);
   if (count < 1) return set(POLAR_ENOMEM);
@@ -578,7 +584,7 @@ polar_status polar_batch_decode_desc(const polar_batch* b, const uint64_t* desc,
   if (!b || nframes < 0) return set(POLAR_EINVAL);
   if (!b->prepared) return set(POLAR_ESTATE);
   if (nframes == 0) return set(POLAR_OK);
-  if (!desc || !llr || !bits || ((uintptr_t)llr & 3u) != 0) return set(POLAR_EINVAL);
+  if (!desc || !llr || !bits || !llr_aligned(b->llr_type, llr)) return set(POLAR_EINVAL);
   if (!on_device(b->device))
     return set_msg(POLAR_ESTATE, "the current device is not the one the batch was prepared on");
   const int rc = polar::batch_launch(b->fn, desc, nframes, llr, bits, b->wave_bytes, b->waves_per_block, b->blocks,

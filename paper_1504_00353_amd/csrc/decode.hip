@@ -39,24 +39,23 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint32_t* __restrict_
 
 int launch_decode(const uint32_t* ops, int nops, int log2n, int kbits, int llr_type, const void* llr, int nframes,
                   uint8_t* bits, void* trace, int waves_per_block, void* stream) {
-  const int wb = wave_lds_bytes(log2n, llr_type == 1 ? 4 : 1);
+  int wb = wave_lds_bytes(log2n, llr_type == 1 ? 4 : 1);
   const dim3 grid((nframes + waves_per_block - 1) / waves_per_block), block(64 * waves_per_block);
   const size_t lds = (size_t)wb * waves_per_block;
-  hipStream_t s = (hipStream_t)stream;
-  if (llr_type == 1)
-    hipLaunchKernelGGL(decode_kernel<PF32>, grid, block, lds, s, ops, nops, log2n, kbits, (const float*)llr,
-                       nframes, bits, (float*)trace, wb);
-  else
-    hipLaunchKernelGGL(decode_kernel<PI8>, grid, block, lds, s, ops, nops, log2n, kbits, (const int8_t*)llr,
-                       nframes, bits, (int8_t*)trace, wb);
-  return (int)hipGetLastError();
+  // the launch's own status: an error left on the thread by an earlier,
+  // unrelated call is neither reported nor cleared here
+  void* args[] = {(void*)&ops, (void*)&nops, (void*)&log2n, (void*)&kbits, (void*)&llr,
+                  (void*)&nframes, (void*)&bits, (void*)&trace, (void*)&wb};
+  const void* fn = llr_type == 1 ? (const void*)decode_kernel<PF32> : (const void*)decode_kernel<PI8>;
+  return (int)hipLaunchKernel(fn, grid, block, args, lds, (hipStream_t)stream);
 }
 
-int set_lds_limit(int llr_type, int bytes) {
-  hipError_t e;
-  if (llr_type == 1)
-    e = hipFuncSetAttribute((const void*)decode_kernel<PF32>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  else
+// Allows the schedule kernels every dynamic LDS size the device offers, so
+// a launch never depends on which code was prepared last.
+int set_lds_limit(int bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)decode_kernel<PF32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     bytes);
+  if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)decode_kernel<PI8>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   return (int)e;
 }

@@ -1,12 +1,16 @@
 // Continuous-batching request server over a prepared polar_batch (C ABI in
 // include/polar.h, polar_server_*).
 //
-// Requests (1..n frames of one code; host LLRs in, host bits out) are
-// admitted first come, first served as soon as device slots for all their
-// frames are free.  Each frame-length class (one per distinct N among the
-// batch's codes) owns a ring of fixed-size frame slots inside one device LLR
-// pool and one device bits pool, so an admitted request holds one contiguous
-// slot range: one host-to-device copy per request in, one copy out.
+// Requests (1..n frames of one code) are admitted first come, first served
+// as soon as the device memory they need is free.  LLRs and results in host
+// memory go through the server's own device pools: each frame-length class
+// (one per distinct N among the batch's codes) owns a ring of fixed-size
+// LLR slots in one device LLR pool and a ring of bits slots in one device
+// bits pool, so such a request holds one contiguous slot range of each ring
+// it needs: one host-to-device copy per request in, one copy out.  LLRs and
+// results already in device memory are read and written in place; they use
+// no slot, and count instead against a byte budget of caller memory that
+// admitted, unfinished requests may reference.
 //
 // polar_server_poll() does all the work on the caller's thread: it retires
 // finished steps (their results are already in pinned host memory), admits
@@ -44,6 +48,13 @@ struct Ring {
     head = tail = used = 0;
     len.assign(slots, 0);
     gap.assign(slots, 0);
+  }
+  // whether alloc(k) would succeed (same rules, nothing changed)
+  bool fits(int k) const {
+    if (k <= 0 || k > n || used + k > n) return false;
+    if (used == 0) return true;
+    if (head >= tail) return n - head >= k || tail >= k;
+    return tail - head >= k;
   }
   int take(int k) {
     const int s = head;
@@ -95,15 +106,18 @@ struct SizeClass {
   int bits_bytes = 0;       // bytes of one bits slot (largest ceil(K/8) of the class)
   size_t llr_base = 0;      // byte offset of slot 0 in the LLR pool
   size_t bits_base = 0;     // byte offset of slot 0 in the bits pool
-  Ring ring;
+  Ring llr_ring;            // LLR slots of requests with host LLRs
+  Ring bits_ring;           // bits slots of requests with host results
 };
 
 struct Request {
   int code = 0, cls = 0, nframes = 0;
-  int slot = -1;            // first slot of its range in the class ring
+  int llr_slot = -1;        // first slot of its range in the class's LLR ring (host LLRs)
+  int bits_slot = -1;       // first slot of its range in the class's bits ring (host results)
   const uint8_t* dev_llr = nullptr;  // LLRs already in device memory (else staged)
   uint8_t* bits = nullptr;  // caller's output: host memory, or device memory if dev_bits
   bool dev_bits = false;
+  size_t dev_bytes = 0;     // caller device memory it references (budgeted)
   size_t stage_off = 0;     // its LLR copy in the pinned staging ring
   size_t stage_len = 0;     // bytes taken there, including a skipped end gap
   size_t stage_end = 0;     // end of its bytes in the ring
@@ -132,6 +146,8 @@ struct polar_server {
   int elem = 1;
   std::vector<int> code_n, code_rb, code_cls;
   std::vector<SizeClass> cls;
+  size_t dev_budget = 0;  // caller device bytes admitted requests may reference
+  size_t dev_used = 0;
   uint8_t* d_llr = nullptr;
   uint8_t* d_bits = nullptr;
   uint8_t* h_bits = nullptr;  // pinned mirror of the bits pool
@@ -215,13 +231,19 @@ void stage_release(polar_server* s, const Request& r) {
   if (s->stage_used == 0) s->stage_head = s->stage_tail = 0;
 }
 
-// Moves waiting requests to admitted while their slots fit (FIFO).
+// Moves waiting requests to admitted while the memory they need is free
+// (FIFO): LLR slots for host LLRs, bits slots for host results, budget
+// bytes for caller device memory.
 void admit(polar_server* s) {
   while (!s->waiting.empty()) {
     Request& r = s->reqs[s->waiting.front()];
-    const int slot = s->cls[r.cls].ring.alloc(r.nframes);
-    if (slot < 0) break;
-    r.slot = slot;
+    SizeClass& c = s->cls[r.cls];
+    if (!r.dev_llr && !c.llr_ring.fits(r.nframes)) break;
+    if (!r.dev_bits && !c.bits_ring.fits(r.nframes)) break;
+    if (s->dev_used + r.dev_bytes > s->dev_budget) break;
+    if (!r.dev_llr) r.llr_slot = c.llr_ring.alloc(r.nframes);
+    if (!r.dev_bits) r.bits_slot = c.bits_ring.alloc(r.nframes);
+    s->dev_used += r.dev_bytes;
     s->admitted.push_back(s->waiting.front());
     s->waiting.pop_front();
   }
@@ -267,8 +289,8 @@ polar_status launch_class(polar_server* s, int ci, int st) {
       continue;
     }
     const SizeClass& c = s->cls[r.cls];
-    const size_t llr_off = c.llr_base + (size_t)r.slot * c.llr_bytes;
-    const size_t bits_off = c.bits_base + (size_t)r.slot * c.bits_bytes;
+    const size_t llr_off = c.llr_base + (size_t)(r.llr_slot < 0 ? 0 : r.llr_slot) * c.llr_bytes;
+    const size_t bits_off = c.bits_base + (size_t)(r.bits_slot < 0 ? 0 : r.bits_slot) * c.bits_bytes;
     // LLR element offset from the pool base: the request's slot for staged
     // requests; for requests already in device memory, the signed distance
     // to the caller's buffer (the kernel's 64-bit address sum wraps to it)
@@ -306,9 +328,9 @@ polar_status launch_class(polar_server* s, int ci, int st) {
     for (int64_t id : step.reqs) {
       const Request& r = s->reqs[id];
       if (r.cls != (int)ci || r.dev_bits) continue;
-      if (lo >= 0 && r.slot < lo) wrapped = true;
-      if (lo < 0 || r.slot < lo) lo = r.slot;
-      hi = std::max(hi, r.slot + r.nframes);
+      if (lo >= 0 && r.bits_slot < lo) wrapped = true;
+      if (lo < 0 || r.bits_slot < lo) lo = r.bits_slot;
+      hi = std::max(hi, r.bits_slot + r.nframes);
     }
     if (lo < 0) continue;
     const SizeClass& c = s->cls[ci];
@@ -316,7 +338,7 @@ polar_status launch_class(polar_server* s, int ci, int st) {
       for (int64_t id : step.reqs) {
         const Request& r = s->reqs[id];
         if (r.cls != (int)ci || r.dev_bits) continue;
-        const size_t off = c.bits_base + (size_t)r.slot * c.bits_bytes;
+        const size_t off = c.bits_base + (size_t)r.bits_slot * c.bits_bytes;
         if (hipMemcpyAsync(s->h_bits + off, s->d_bits + off, (size_t)r.nframes * c.bits_bytes,
                            hipMemcpyDeviceToHost, stream) != hipSuccess)
           return POLAR_EDEVICE;
@@ -369,11 +391,16 @@ polar_status retire(polar_server* s, int64_t* done, int cap, int* ndone, std::ve
       Request& r = it->second;
       const SizeClass& c = s->cls[r.cls];
       const int rb = s->code_rb[r.code];
-      const uint8_t* src = s->h_bits + c.bits_base + (size_t)r.slot * c.bits_bytes;
-      if (!r.dev_bits)
+      if (!r.dev_bits) {
+        const uint8_t* src = s->h_bits + c.bits_base + (size_t)r.bits_slot * c.bits_bytes;
         for (int j = 0; j < r.nframes; ++j) memcpy(r.bits + (size_t)j * rb, src + (size_t)j * c.bits_bytes, rb);
-      s->cls[r.cls].ring.release(r.slot);
-      if (!r.dev_llr) stage_release(s, r);
+        s->cls[r.cls].bits_ring.release(r.bits_slot);
+      }
+      if (!r.dev_llr) {
+        s->cls[r.cls].llr_ring.release(r.llr_slot);
+        stage_release(s, r);
+      }
+      s->dev_used -= r.dev_bytes;
       if (*ndone < cap && done) done[*ndone] = id;
       if (all) all->push_back(id);
       ++*ndone;
@@ -390,9 +417,10 @@ polar_status retire(polar_server* s, int64_t* done, int cap, int* ndone, std::ve
 extern "C" {
 
 polar_server* polar_server_create(const polar_batch* batch, const polar_code* const* codes, int ncodes,
-                                  int slots_per_class, int streams, size_t staging_bytes) {
-  if (!batch || !codes || ncodes < 1 || ncodes != (int)batch->plans.size() || slots_per_class < 1 || streams < 1 ||
-      streams > 8 || staging_bytes < 4096 || !batch->prepared) {
+                                  int slots_per_class, int streams, size_t staging_bytes, size_t device_bytes) {
+  if (!batch || !codes || ncodes < 1 || ncodes != (int)batch->plans.size() || slots_per_class < 0 ||
+      (slots_per_class == 0 && device_bytes == 0) || streams < 1 || streams > 8 || staging_bytes < 4096 ||
+      !batch->prepared) {
     polar_set_status(!batch || (batch && !batch->prepared) ? (batch ? POLAR_ESTATE : POLAR_EINVAL) : POLAR_EINVAL);
     return nullptr;
   }
@@ -429,16 +457,24 @@ polar_server* polar_server_create(const polar_batch* batch, const polar_code* co
       s->cls[c].bits_bytes = std::max(s->cls[c].bits_bytes, (codes[i]->plan.k + 7) / 8);
     }
     if (st == POLAR_OK) {
-      size_t llr_total = 0, bits_total = 0;
+      // pools of at least 256 bytes: their bases anchor the descriptor offsets
+      size_t llr_total = 256, bits_total = 256;
+      size_t cap = 0;  // most frames of one class admitted at once
       for (SizeClass& c : s->cls) {
         c.bits_bytes = (c.bits_bytes + 15) & ~15;
         c.llr_base = llr_total;
         c.bits_base = bits_total;
         llr_total += (size_t)slots_per_class * c.llr_bytes;
         bits_total += (size_t)slots_per_class * c.bits_bytes;
-        c.ring.init(slots_per_class);
+        c.llr_ring.init(slots_per_class);
+        c.bits_ring.init(slots_per_class);
+        // frames with host LLRs or host results hold a slot of one ring
+        // each; frames with both in device memory cost at least N LLR bytes
+        cap = std::max(cap, 2 * (size_t)slots_per_class + device_bytes / (size_t)c.llr_bytes);
       }
-      s->desc_cap = slots_per_class * (int)s->cls.size();
+      if (cap > ((size_t)1 << 24)) cap = (size_t)1 << 24;
+      s->desc_cap = (int)cap;
+      s->dev_budget = device_bytes;
       s->sort_tmp.reserve(2 * (size_t)s->desc_cap);  // steps never allocate for it
       s->stage_size = staging_bytes;
       if (hipMalloc((void**)&s->d_llr, llr_total) != hipSuccess ||
@@ -483,7 +519,7 @@ polar_status polar_server_submit(polar_server* s, int code_index, int nframes, c
     return polar_set_status(POLAR_EINVAL);
   if (s->failed) return polar_set_status(POLAR_EDEVICE);
   const SizeClass& c = s->cls[s->code_cls[code_index]];
-  if (nframes > c.ring.n) return polar_set_status(POLAR_EINVAL);  // could never be admitted
+  const bool bits_on_device = (where & POLAR_SERVER_BITS_DEVICE) != 0;
   if (llr_on_device && ((uintptr_t)llr % (uintptr_t)s->elem) != 0) return polar_set_status(POLAR_EINVAL);
   const size_t bytes = (size_t)nframes * c.llr_bytes;
   Request r;
@@ -491,7 +527,12 @@ polar_status polar_server_submit(polar_server* s, int code_index, int nframes, c
   r.cls = s->code_cls[code_index];
   r.nframes = nframes;
   r.bits = bits;
-  r.dev_bits = (where & POLAR_SERVER_BITS_DEVICE) != 0;
+  r.dev_bits = bits_on_device;
+  r.dev_bytes = (llr_on_device ? bytes : 0) + (bits_on_device ? (size_t)nframes * s->code_rb[code_index] : 0);
+  // requests that could never be admitted
+  if ((!llr_on_device && nframes > c.llr_ring.n) || (!bits_on_device && nframes > c.bits_ring.n) ||
+      r.dev_bytes > s->dev_budget || (size_t)nframes > (size_t)s->desc_cap)
+    return polar_set_status(POLAR_EINVAL);
   if (llr_on_device) {
     r.dev_llr = (const uint8_t*)llr;
   } else {
@@ -601,6 +642,13 @@ polar_status polar_server_pending(const polar_server* s, int* waiting, int* admi
   if (waiting) *waiting = (int)s->waiting.size();
   if (admitted) *admitted = (int)s->admitted.size();
   if (inflight_steps) *inflight_steps = (int)s->inflight.size();
+  return polar_set_status(POLAR_OK);
+}
+
+polar_status polar_server_device_bytes(const polar_server* s, size_t* in_use, size_t* budget) {
+  if (!s) return polar_set_status(POLAR_EINVAL);
+  if (in_use) *in_use = s->dev_used;
+  if (budget) *budget = s->dev_budget;
   return polar_set_status(POLAR_OK);
 }
 

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+from bounds import forward_error_scale
 from frames import make_frames
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -278,25 +279,6 @@ def test_fer_falls_with_snr():
         fer.append(np.mean((u_hat != u).any(axis=1)))
     assert fer[0] > fer[1] > fer[2]
     assert fer[0] > 0.3 and fer[2] < 0.1
-
-
-def forward_error_scale(llr64):
-    """Per-position bound on the magnitude of every alpha computed at that
-    position: f passes one operand through (scale max), g adds two (scale
-    sum).  Independent of the bit decisions; the maximum over all tree nodes
-    covering a position bounds the leaf there."""
-    acc = np.zeros_like(llr64)
-
-    def walk(a, o):
-        n = a.shape[-1]
-        acc[..., o:o + n] = np.maximum(acc[..., o:o + n], a)
-        if n == 1:
-            return
-        h = n // 2
-        walk(np.maximum(a[..., :h], a[..., h:]), o)
-        walk(a[..., :h] + a[..., h:], o + h)
-    walk(np.abs(llr64), 0)
-    return acc
 
 
 @pytest.mark.parametrize("n,k,d,algo", [(1024, 512, 2.5, "sc"), (4096, 3686, 4.0, "fastssc"),

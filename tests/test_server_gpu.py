@@ -1,7 +1,7 @@
 """Continuous-batching request server: every result equals the oracle and
-equals the same request decoded alone; requests wait for device slots when
-memory is short; staging back-pressure; LLRs read in place from device
-memory."""
+equals the same request decoded alone; requests wait for device memory when
+it is short (pool slots for host buffers, a byte budget for device-resident
+ones); staging back-pressure; LLRs read in place from device memory."""
 import numpy as np
 import pytest
 
@@ -146,6 +146,7 @@ def test_server_device_outputs_and_trace_replay(serving):
         assert np.array_equal(o.cpu().numpy(), oracle_rows(frozens[c], l))
     # device outputs through submit/poll as well
     outs2 = [torch.zeros_like(o) for o in outs]
+    torch.cuda.synchronize()  # the fills run on torch's stream; the server's streams do not wait for it
     for (c, _), t, o in zip(reqs, llrs, outs2):
         assert srv.submit(c, t, o) is not None
         srv.poll()
@@ -181,3 +182,67 @@ def test_server_short_code_not_behind_long(serving):
     assert seen[isml] <= seen[ib]
     assert np.array_equal(bb, oracle_rows(frozens[big], lb))
     assert np.array_equal(bs, oracle_rows(frozens[small], ls))
+
+
+def test_device_requests_need_no_pool_slots(serving):
+    """Device-resident requests take no LLR or bits slot: with 64 slots per
+    frame length, a 64-frame host request and a 64-frame device request of
+    the same length are both admitted by one poll (the host request alone
+    fills the LLR ring)."""
+    codes, batch, frozens = serving
+    big = int(np.argmax([c.n for c in codes]))
+    _, _, l1 = make_frames(frozens[big], 81, 64, 4.0, "i8")
+    _, _, l2 = make_frames(frozens[big], 82, 64, 4.0, "i8")
+    srv = Server(batch, slots_per_class=64, streams=2, device_bytes=64 << 20)
+    b1 = np.zeros((64, codes[big].row_bytes), np.uint8)
+    d2 = torch.from_numpy(l2).cuda()
+    o2 = torch.zeros((64, codes[big].row_bytes), dtype=torch.uint8, device="cuda")
+    assert srv.submit(big, l1, b1) is not None
+    assert srv.submit(big, d2, o2) is not None
+    srv.poll()
+    assert srv.pending()[0] == 0, "the device request waited for a pool slot"
+    srv.drain()
+    torch.cuda.synchronize()
+    assert srv.device_bytes()[0] == 0
+    assert np.array_equal(b1, oracle_rows(frozens[big], l1))
+    assert np.array_equal(o2.cpu().numpy(), oracle_rows(frozens[big], l2))
+    srv.close()
+
+
+def test_device_byte_budget_admission(serving):
+    """The byte budget of caller device memory: a budget that holds one
+    64-frame device-resident request of the longest code admits the first of
+    two such requests and holds the second until the first retires; a
+    request larger than the whole budget is refused at submit."""
+    from paper_1504_00353_amd.binding import PolarError
+    codes, batch, frozens = serving
+    big = int(np.argmax([c.n for c in codes]))
+    n, rb = codes[big].n, codes[big].row_bytes
+    per_req = 64 * (n + rb)
+    srv = Server(batch, slots_per_class=0, streams=2, device_bytes=per_req)
+    assert srv.device_bytes() == (0, per_req)
+    llrs, outs = [], []
+    for seed in (83, 84):
+        _, _, l = make_frames(frozens[big], seed, 64, 4.0, "i8")
+        llrs.append(l)
+        outs.append(torch.zeros((64, rb), dtype=torch.uint8, device="cuda"))
+    dev = [torch.from_numpy(l).cuda() for l in llrs]
+    for d, o in zip(dev, outs):
+        assert srv.submit(big, d, o) is not None
+    srv.poll()
+    waiting, admitted, inflight = srv.pending()
+    assert waiting == 1, (waiting, admitted, inflight)
+    assert srv.device_bytes()[0] == per_req
+    srv.drain()
+    torch.cuda.synchronize()
+    assert srv.device_bytes()[0] == 0
+    for l, o in zip(llrs, outs):
+        assert np.array_equal(o.cpu().numpy(), oracle_rows(frozens[big], l))
+    # 65 frames exceed the budget: never admissible
+    _, _, l3 = make_frames(frozens[big], 85, 65, 4.0, "i8")
+    with pytest.raises(PolarError):
+        srv.submit(big, torch.from_numpy(l3).cuda(), torch.zeros((65, rb), dtype=torch.uint8, device="cuda"))
+    # host buffers need pool slots, and this server has none
+    with pytest.raises(PolarError):
+        srv.submit(big, llrs[0][:1], np.zeros((1, rb), np.uint8))
+    srv.close()
