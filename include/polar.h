@@ -300,6 +300,27 @@ polar_status polar_batch_decode(const polar_batch* batch, const void* llr, uint8
 polar_status polar_batch_decode_desc(const polar_batch* batch, const uint64_t* desc, int nframes,
                                      const void* llr, uint8_t* bits, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): decodes nframes
+ * frames described by three arrays in DEVICE memory -- code_index[i] (int32),
+ * llr_offset[i] (elements) and bits_offset[i] (bytes), as for
+ * polar_batch_set_frames() -- in one launch, with the same results as
+ * polar_batch_set_frames() + polar_batch_decode() on those frames.  Calls
+ * no hipMalloc/hipFree: the descriptor queue is a fixed device array of the
+ * library (4 MiB per device, held until the process ends), filled by a small
+ * kernel on the stream, so at most 262144 frames per call (more:
+ * POLAR_EINVAL).  Frames are decoded in the given order (no longest-first
+ * ordering).  A frame whose code index is out of range, or whose offset is
+ * negative (bits offset >= 2^56), is skipped and its output row is not
+ * written; offsets must otherwise index inside llr and bits.  Every call on
+ * one device shares the one array: calls that overlap on a device (other
+ * streams, other threads) race and must be ordered by the caller.
+ * Asynchronous, capturable (two kernel launches, no memset).  Errors:
+ * POLAR_EINVAL, POLAR_ESTATE (not prepared, other device), POLAR_EDEVICE. */
+polar_status polar_batch_decode_frames_noalloc(const polar_batch* batch, int nframes, const int32_t* code_index,
+                                               const int64_t* llr_offset, const int64_t* bits_offset,
+                                               const void* llr, uint8_t* bits, void* stream);
+
 /* Autotuner: times launch shapes (1, 2 or 4 frames per workgroup; a grid
  * that fills the chip's wave slots once or twice, or one wave per frame)
  * on the frames of the last polar_batch_set_frames() and keeps the

@@ -26,6 +26,7 @@ EXPORTS = [
     "polar_build_kernel",
     "polar_last_message", "polar_batch_create", "polar_batch_build_kernel", "polar_batch_prepare",
     "polar_batch_set_frames", "polar_batch_decode", "polar_batch_decode_desc", "polar_batch_tune",
+    "polar_batch_decode_frames_noalloc",
     "polar_batch_launch_shape", "polar_batch_destroy", "polar_server_create", "polar_server_submit",
     "polar_server_poll", "polar_server_pending", "polar_server_destroy", "polar_server_run_trace",
     "polar_server_device_bytes",
@@ -87,6 +88,7 @@ def _lib():
         L.polar_batch_decode.argtypes = [P, P, P, P]
         L.polar_batch_decode_desc.argtypes = [P, P, I, P, P, P]
         L.polar_batch_tune.argtypes = [P, P, P, P]
+        L.polar_batch_decode_frames_noalloc.argtypes = [P, I, P, P, P, P, P, P]
         L.polar_batch_launch_shape.argtypes = [P, P, P, P]
         L.polar_batch_destroy.argtypes = [P]
         L.polar_batch_destroy.restype = None
@@ -316,6 +318,24 @@ class Batch:
         _check(_lib().polar_batch_decode_desc(self._h, ctypes.c_void_p(desc.data_ptr()), int(nframes),
                                               ctypes.c_void_p(llr.data_ptr()), ctypes.c_void_p(bits.data_ptr()),
                                               _stream_handle(stream)), "polar_batch_decode_desc")
+        return bits
+
+    def decode_frames_noalloc(self, code_index, llr_offset, bits_offset, llr, bits, stream=None):
+        """polar_batch_decode_frames_noalloc: the frames' code indices (int32)
+        and LLR / bits offsets (int64) are 1-D CUDA tensors of one length;
+        llr and bits as for decode."""
+        import torch
+        n = int(code_index.numel())
+        if not (code_index.dtype == torch.int32 and llr_offset.dtype == torch.int64 == bits_offset.dtype and
+                llr_offset.numel() == n == bits_offset.numel()):
+            raise ValueError("code_index int32, llr_offset and bits_offset int64, all of one length")
+        for t in (code_index, llr_offset, bits_offset):
+            if not t.is_contiguous():
+                raise ValueError("frame arrays must be contiguous")
+        _check(_lib().polar_batch_decode_frames_noalloc(
+            self._h, n, ctypes.c_void_p(code_index.data_ptr()), ctypes.c_void_p(llr_offset.data_ptr()),
+            ctypes.c_void_p(bits_offset.data_ptr()), ctypes.c_void_p(llr.data_ptr()),
+            ctypes.c_void_p(bits.data_ptr()), _stream_handle(stream)), "polar_batch_decode_frames_noalloc")
         return bits
 
     def tune(self, llr, bits, stream=None):

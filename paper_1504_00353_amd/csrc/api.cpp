@@ -10,6 +10,7 @@
 
 #include "../../include/polar.h"
 #include "internal.h"
+#include "noalloc.h"
 
 namespace polar {
 int launch_decode(const uint32_t* ops, int nops, int log2n, int kbits, int llr_type, const void* llr, int nframes,
@@ -587,6 +588,27 @@ polar_status polar_batch_decode_desc(const polar_batch* b, const uint64_t* desc,
   if (!desc || !llr || !bits || !llr_aligned(b->llr_type, llr)) return set(POLAR_EINVAL);
   if (!on_device(b->device))
     return set_msg(POLAR_ESTATE, "the current device is not the one the batch was prepared on");
+  const int rc = polar::batch_launch(b->fn, desc, nframes, llr, bits, b->wave_bytes, b->waves_per_block, b->blocks,
+                                     stream);
+  return set(rc == 0 ? POLAR_OK : POLAR_EDEVICE);
+}
+
+polar_status polar_batch_decode_frames_noalloc(const polar_batch* b, int nframes, const int32_t* code_index,
+                                               const int64_t* llr_offset, const int64_t* bits_offset, const void* llr,
+                                               uint8_t* bits, void* stream) {
+  if (!b || nframes < 0) return set(POLAR_EINVAL);
+  if (nframes > polar::kNoallocMaxFrames)
+    return set_msg(POLAR_EINVAL, "polar_batch_decode_frames_noalloc takes at most 262144 frames per call");
+  if (!b->prepared) return set(POLAR_ESTATE);
+  if (nframes == 0) return set(POLAR_OK);
+  if (!code_index || !llr_offset || !bits_offset || !llr || !bits || !llr_aligned(b->llr_type, llr))
+    return set(POLAR_EINVAL);
+  if (!on_device(b->device))
+    return set_msg(POLAR_ESTATE, "the current device is not the one the batch was prepared on");
+  void* desc = polar::noalloc_scratch(b->device);
+  if (!desc) return set_msg(POLAR_EDEVICE, "no device address for the descriptor array");
+  if (polar::noalloc_pack(desc, nframes, (int)b->plans.size(), code_index, llr_offset, bits_offset, stream) != 0)
+    return set(POLAR_EDEVICE);
   const int rc = polar::batch_launch(b->fn, desc, nframes, llr, bits, b->wave_bytes, b->waves_per_block, b->blocks,
                                      stream);
   return set(rc == 0 ? POLAR_OK : POLAR_EDEVICE);
