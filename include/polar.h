@@ -171,6 +171,14 @@ const char* polar_strerror(polar_status status);
  * the library on this thread. */
 const char* polar_last_message(void);
 
+/* Test hook (failure handling): after `after` more allocations succeed, the
+ * next allocation the library makes -- a code, batch or server object,
+ * device memory or pinned host memory -- fails as if memory ran out (once;
+ * then allocations succeed again).  The call that makes it returns
+ * POLAR_ENOMEM (or NULL with polar_last_status() == POLAR_ENOMEM) and keeps
+ * nothing it allocated.  after < 0 disarms the hook.  Process wide. */
+polar_status polar_debug_fail_allocations(int after);
+
 int polar_n(const polar_code* code); /* 0 for NULL */
 int polar_k(const polar_code* code); /* 0 for NULL */
 

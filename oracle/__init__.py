@@ -15,7 +15,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
-_SO = os.path.join(_HERE, "liboracle.so")
+# POLAR_ORACLE_LIBRARY: another build of oracle.cpp (the sanitizer test)
+_SO = os.environ.get("POLAR_ORACLE_LIBRARY") or os.path.join(_HERE, "liboracle.so")
 
 ALGO = {"fastssc": 0, "sc": 1}
 KIND = {"rate1": 1, "rep": 2, "spc": 3}

@@ -9,7 +9,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SO_PATH = os.path.join(_HERE, "libpolar.so")
+# POLAR_LIBRARY: another build of the same library (the sanitizer test
+# loads an ASan/UBSan build of the host code through it)
+SO_PATH = os.environ.get("POLAR_LIBRARY") or os.path.join(_HERE, "libpolar.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ECOMPILE, EAGAIN = 0, 1, 2, 3, 4, 5, 6
 ALGO = {"fastssc": 0, "sc": 1}
@@ -26,7 +28,7 @@ EXPORTS = [
     "polar_build_kernel",
     "polar_last_message", "polar_batch_create", "polar_batch_build_kernel", "polar_batch_prepare",
     "polar_batch_set_frames", "polar_batch_decode", "polar_batch_decode_desc", "polar_batch_tune",
-    "polar_batch_decode_frames_noalloc",
+    "polar_batch_decode_frames_noalloc", "polar_debug_fail_allocations",
     "polar_batch_launch_shape", "polar_batch_destroy", "polar_server_create", "polar_server_submit",
     "polar_server_poll", "polar_server_pending", "polar_server_destroy", "polar_server_run_trace",
     "polar_server_device_bytes",
@@ -73,6 +75,7 @@ def _lib():
         L.polar_strerror.restype = ctypes.c_char_p
         L.polar_last_message.argtypes = []
         L.polar_last_message.restype = ctypes.c_char_p
+        L.polar_debug_fail_allocations.argtypes = [I]
         L.polar_n.argtypes = [P]
         L.polar_k.argtypes = [P]
         L.polar_frozen_mask.argtypes = [P, P]

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <new>
 #include <string>
@@ -16,6 +17,41 @@ namespace polar {
 int launch_decode(const uint32_t* ops, int nops, int log2n, int kbits, int llr_type, const void* llr, int nframes,
                   uint8_t* bits, void* trace, int waves_per_block, void* stream);
 int set_lds_limit(int bytes);
+}  // namespace polar
+
+namespace polar {
+
+namespace {
+// allocations to let through before the armed failure; -1: none armed
+std::atomic<long> g_fail_countdown{-1};
+}  // namespace
+
+void arm_alloc_failure(int after) { g_fail_countdown.store(after < 0 ? -1 : (long)after); }
+
+bool alloc_fails() {
+  long c = g_fail_countdown.load();
+  while (c >= 0) {
+    if (g_fail_countdown.compare_exchange_weak(c, c - 1)) return c == 0;
+  }
+  return false;
+}
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+  if (alloc_fails()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
+hipError_t pinned_malloc(void** p, size_t bytes) {
+  if (alloc_fails()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipHostMalloc(p, bytes, 0);
+}
+
 }  // namespace polar
 
 namespace {
@@ -56,7 +92,7 @@ int log2_exact(int n) {
 }
 
 polar_code* make_code(int n, std::vector<uint8_t>&& frozen) {
-  polar_code* c = new (std::nothrow) polar_code;
+  polar_code* c = polar::alloc_fails() ? nullptr : new (std::nothrow) polar_code;
   if (!c) {
     set(POLAR_ENOMEM);
     return nullptr;
@@ -251,7 +287,7 @@ polar_status polar_prepare(polar_code* c) {
     if (polar::set_lds_limit(lds_max) != hipSuccess) return set(POLAR_EDEVICE);
     const size_t bytes = c->plan.dops.size() * sizeof(uint32_t);
     uint32_t* d = nullptr;
-    if (hipMalloc((void**)&d, bytes ? bytes : 4) != hipSuccess) return set(POLAR_ENOMEM);
+    if (polar::dev_malloc((void**)&d, bytes ? bytes : 4) != hipSuccess) return set(POLAR_ENOMEM);
     if (bytes && hipMemcpy(d, c->plan.dops.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
       (void)hipFree(d);
       return set(POLAR_EDEVICE);
@@ -279,6 +315,11 @@ void polar_destroy(polar_code* c) {
 }
 
 polar_status polar_last_status(void) { return g_last; }
+
+polar_status polar_debug_fail_allocations(int after) {
+  polar::arm_alloc_failure(after);
+  return set(POLAR_OK);
+}
 
 const char* polar_last_message(void) { return g_message.c_str(); }
 
@@ -473,7 +514,7 @@ polar_batch* polar_batch_create(const polar_code* const* codes, int ncodes) {
       set(POLAR_EINVAL);
       return nullptr;
     }
-  polar_batch* b = new (std::nothrow) polar_batch;
+  polar_batch* b = polar::alloc_fails() ? nullptr : new (std::nothrow) polar_batch;
   if (!b) {
     set(POLAR_ENOMEM);
     return nullptr;
@@ -568,7 +609,7 @@ polar_status polar_batch_set_frames(polar_batch* b, int nframes, const int32_t* 
   if (hipDeviceSynchronize() != hipSuccess) return set(POLAR_EDEVICE);
   if (nframes > b->desc_cap) {
     unsigned long long* d = nullptr;
-    if (hipMalloc((void**)&d, desc.size() * sizeof(unsigned long long)) != hipSuccess) return set(POLAR_ENOMEM);
+    if (polar::dev_malloc((void**)&d, desc.size() * sizeof(unsigned long long)) != hipSuccess) return set(POLAR_ENOMEM);
     if (b->d_desc) (void)hipFree(b->d_desc);
     b->d_desc = d;
     b->desc_cap = nframes;

@@ -40,3 +40,14 @@ struct polar_batch {
 
 // Records a status for polar_last_status() and returns it.
 polar_status polar_set_status(polar_status s);
+
+namespace polar {
+// Every allocation the library makes (its objects, device memory, pinned
+// host memory) asks this first; true when polar_debug_fail_allocations()
+// has armed a failure for this allocation.
+bool alloc_fails();
+void arm_alloc_failure(int after);
+// hipMalloc / hipHostMalloc through the allocation-failure hook.
+hipError_t dev_malloc(void** p, size_t bytes);
+hipError_t pinned_malloc(void** p, size_t bytes);
+}  // namespace polar

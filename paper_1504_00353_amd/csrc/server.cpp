@@ -424,7 +424,7 @@ polar_server* polar_server_create(const polar_batch* batch, const polar_code* co
     polar_set_status(!batch || (batch && !batch->prepared) ? (batch ? POLAR_ESTATE : POLAR_EINVAL) : POLAR_EINVAL);
     return nullptr;
   }
-  polar_server* s = new (std::nothrow) polar_server;
+  polar_server* s = polar::alloc_fails() ? nullptr : new (std::nothrow) polar_server;
   if (!s) {
     polar_set_status(POLAR_ENOMEM);
     return nullptr;
@@ -477,12 +477,12 @@ polar_server* polar_server_create(const polar_batch* batch, const polar_code* co
       s->dev_budget = device_bytes;
       s->sort_tmp.reserve(2 * (size_t)s->desc_cap);  // steps never allocate for it
       s->stage_size = staging_bytes;
-      if (hipMalloc((void**)&s->d_llr, llr_total) != hipSuccess ||
-          hipMalloc((void**)&s->d_bits, bits_total) != hipSuccess ||
-          hipMalloc((void**)&s->d_desc, (size_t)streams * s->desc_cap * 16) != hipSuccess ||
-          hipHostMalloc((void**)&s->h_bits, bits_total, 0) != hipSuccess ||
-          hipHostMalloc((void**)&s->h_stage, staging_bytes, 0) != hipSuccess ||
-          hipHostMalloc((void**)&s->h_desc, (size_t)streams * s->desc_cap * 16, 0) != hipSuccess)
+      if (polar::dev_malloc((void**)&s->d_llr, llr_total) != hipSuccess ||
+          polar::dev_malloc((void**)&s->d_bits, bits_total) != hipSuccess ||
+          polar::dev_malloc((void**)&s->d_desc, (size_t)streams * s->desc_cap * 16) != hipSuccess ||
+          polar::pinned_malloc((void**)&s->h_bits, bits_total) != hipSuccess ||
+          polar::pinned_malloc((void**)&s->h_stage, staging_bytes) != hipSuccess ||
+          polar::pinned_malloc((void**)&s->h_desc, (size_t)streams * s->desc_cap * 16) != hipSuccess)
         st = POLAR_ENOMEM;
       for (int i = 0; i < streams && st == POLAR_OK; ++i) {
         hipStream_t hs = nullptr;

@@ -5,50 +5,34 @@ frame-error rates of 8-bit fixed point vs float32 LLRs.
 
     python -m paper_1504_00353_amd.study [--frames F] [--fer-frames M]
 
-Frames are synthetic: uniform information bits, BPSK over AWGN, generated
-on the GPU with torch (random codewords, encoded with the butterfly of
-Sec. II-A in torch ops); LLRs as in the benchmark (6-bit quantiser for
-int8).  Prints markdown tables.
+Frames are synthetic and generated on the host: seeded uniform
+information bits, the codeword from the library's encoder (polar_encode),
+BPSK over AWGN (``inputs.channel_frames``); LLRs as in the benchmark (6-bit
+quantiser for int8; the int8 and float32 FER columns decode the same
+channel samples).  Prints markdown tables.
 """
 import argparse
-import time
+import os
 
 import numpy as np
 
+from . import inputs, synth
 
-def encode_torch(u):
-    """x = u G_N over the last axis (x[i] ^= x[i + h] for bit h of i clear)."""
-    x = u.clone()
-    n = x.shape[1]
-    h = 1
-    while h < n:
-        v = x.view(x.shape[0], n // (2 * h), 2, h)
-        v[:, :, 0, :] ^= v[:, :, 1, :]
-        h *= 2
-    return x
+SEED = 2015
+THREADS = min(16, len(os.sched_getaffinity(0)))
 
 
-def channel_frames(code, frames, ebn0_db, llr, gen):
+def channel_frames(code, frames, ebn0_db, llr, first=0, seed=SEED):
+    """(information bits, LLR tensor on the GPU) of frames first ..
+    first + frames - 1 of the study's stream for this code."""
     import torch
-    frozen = torch.from_numpy(code.frozen().astype(bool)).cuda()
-    info = torch.randint(0, 2, (frames, code.k), generator=gen, device="cuda", dtype=torch.uint8)
-    u = torch.zeros((frames, code.n), dtype=torch.uint8, device="cuda")
-    u[:, ~frozen] = info
-    x = encode_torch(u)
-    rate = code.k / code.n
-    sigma = (1.0 / (2.0 * rate * 10.0 ** (ebn0_db / 10.0))) ** 0.5
-    y = (1.0 - 2.0 * x.double()) + sigma * torch.randn(x.shape, generator=gen, device="cuda", dtype=torch.float64)
-    l = (2.0 * y / sigma ** 2).float()
-    if llr == "i8":
-        q = torch.sign(2.0 * l) * torch.floor(torch.abs(2.0 * l) + 0.5)
-        l = torch.clamp(q, -31, 31).to(torch.int8)
-    return info, l.contiguous()
+    l32, info = inputs.channel_frames(code, seed, np.arange(first, first + frames), ebn0_db, THREADS)
+    l = synth.quantize6(l32) if llr == "i8" else l32
+    return info, torch.from_numpy(l).cuda()
 
 
-def unpack(out, k):
-    import torch
-    bits = torch.stack([(out >> b) & 1 for b in range(8)], dim=2).reshape(out.shape[0], -1)
-    return bits[:, :k]
+def frame_errors(out, info):
+    return int((synth.unpack_bits(out.cpu().numpy(), info.shape[1]) != info).any(axis=1).sum())
 
 
 def speed(code, l, prewarm_s=0.25):
@@ -87,8 +71,6 @@ def main():
     ap.add_argument("--frames", type=int, default=4096)
     ap.add_argument("--fer-frames", type=int, default=100000)
     args = ap.parse_args()
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(2015)
 
     print("## Decoding speed (int8, %d frames per launch; latency = one frame per launch, kernel time)\n" % args.frames)
     print("| code | algorithm | kernel | info Gb/s | latency us | ops |")
@@ -99,7 +81,7 @@ def main():
                 if algo == "sc" and n > 2048:
                     continue  # plain SC schedules of N = 32768 are ~65,000 ops
                 code = Code(n, k, d, algo=algo, llr="i8", kernel=kernel)
-                _, l = channel_frames(code, args.frames, d, "i8", gen)
+                _, l = channel_frames(code, args.frames, d, "i8")
                 gbps, lat = speed(code, l)
                 print("| (%d,%d) | %s | %s | %.1f | %.1f | %d |" % (n, k, "SC" if algo == "sc" else "Fast-SSC", kernel,
                                                                      gbps, lat, len(code.schedule())))
@@ -112,7 +94,7 @@ def main():
         for kernel in ("schedule", "unrolled"):
             for fused in (False, True):
                 code = Code(n, k, d, llr="i8", kernel=kernel, fused=fused)
-                _, l = channel_frames(code, args.frames, d, "i8", gen)
+                _, l = channel_frames(code, args.frames, d, "i8")
                 gbps, lat = speed(code, l)
                 print("| (%d,%d) | %s | %s | %d | %.1f | %.1f |" % (n, k, kernel, "yes" if fused else "no",
                                                                    len(code.device_schedule()), gbps, lat))
@@ -125,19 +107,19 @@ def main():
                          (32768, 29492, 4.0, (4.0, 4.25, 4.5))):
         codes = {llr: Code(n, k, d, llr=llr) for llr in ("i8", "f32")}
         for eb in pts:
-            fer = {}
-            for llr, code in codes.items():
-                errs, done = 0, 0
-                g2 = torch.Generator(device="cuda")
-                g2.manual_seed(int(eb * 1000) + n)
-                chunk = max(1, min(args.fer_frames, (1 << 28) // (n * 8)))
-                while done < args.fer_frames:
-                    m = min(chunk, args.fer_frames - done)
-                    info, l = channel_frames(code, m, eb, llr, g2)
-                    out = code.decode(l)
-                    errs += int((unpack(out, k) != info).any(dim=1).sum())
-                    done += m
-                fer[llr] = errs / done
+            errs = {"i8": 0, "f32": 0}
+            chunk = max(1, min(args.fer_frames, (1 << 27) // n))
+            first = 0
+            while first < args.fer_frames:
+                m = min(chunk, args.fer_frames - first)
+                # one set of channel samples, decoded from float32 and from 6-bit int8 LLRs
+                l32, info = inputs.channel_frames(codes["f32"], SEED + int(eb * 1000), np.arange(first, first + m),
+                                                  eb, THREADS)
+                for llr, code in codes.items():
+                    l = synth.quantize6(l32) if llr == "i8" else l32
+                    errs[llr] += frame_errors(code.decode(torch.from_numpy(l).cuda()), info)
+                first += m
+            fer = {llr: e / args.fer_frames for llr, e in errs.items()}
             print("| (%d,%d) | %.2f | %.2e | %.2e |" % (n, k, eb, fer["i8"], fer["f32"]))
 
 

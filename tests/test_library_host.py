@@ -289,3 +289,52 @@ def test_configure_resets_layout():
     assert L.polar_set_layout(c.handle, 2) == binding.OK
     assert L.polar_set_fused_nodes(c.handle, 0) == binding.OK
     assert L.polar_set_layout(c.handle, 3) == binding.EINVAL
+
+
+def test_allocation_failure_hook_objects():
+    """Failure handling: an armed allocation failure makes the object
+    allocation of polar_construct / polar_batch_create return NULL with
+    POLAR_ENOMEM, once; the next call succeeds."""
+    L = binding.lib()
+    try:
+        assert L.polar_debug_fail_allocations(0) == binding.OK
+        assert not L.polar_construct(64, 32, 2.5)
+        assert L.polar_last_status() == binding.ENOMEM
+        h = L.polar_construct(64, 32, 2.5)
+        assert h
+        L.polar_destroy(h)
+        c = binding.Code(64, 32, 2.5, prepare=False)
+        arr = (ctypes.c_void_p * 1)(c.handle.value)
+        L.polar_debug_fail_allocations(0)
+        assert not L.polar_batch_create(arr, 1)
+        assert L.polar_last_status() == binding.ENOMEM
+        b = L.polar_batch_create(arr, 1)
+        assert b
+        L.polar_batch_destroy(b)
+        # the countdown: the second allocation from now fails
+        L.polar_debug_fail_allocations(1)
+        h1 = L.polar_construct(64, 32, 2.5)
+        assert h1
+        assert not L.polar_construct(64, 32, 2.5)
+        assert L.polar_last_status() == binding.ENOMEM
+        L.polar_destroy(h1)
+        L.polar_debug_fail_allocations(-1)
+        h = L.polar_construct(64, 32, 2.5)
+        assert h
+        L.polar_destroy(h)
+    finally:
+        L.polar_debug_fail_allocations(-1)
+
+
+@pytest.mark.parametrize("n,k,d", [(1024, 512, 2.5), (4096, 3686, 4.0)])
+def test_benchmark_inputs_match_oracle_encoded_frames(n, k, d):
+    """The benchmark's and the study's channel frames (library encoder,
+    threaded) are the frames the tests build with the oracle's encoder."""
+    from frames import make_frames
+    from paper_1504_00353_amd import inputs
+    c = binding.Code(n, k, d, prepare=False)
+    ids = np.arange(37) * 3 + 5
+    l32, info = inputs.channel_frames(c, 11, ids, d + 0.5, threads=4)
+    u, _, ref = make_frames(c.frozen(), 11, ids, d + 0.5, llr="f32")
+    assert np.array_equal(l32, ref)
+    assert np.array_equal(info, u[:, c.frozen() == 0])
