@@ -288,6 +288,190 @@ def serving_bench(seconds=1.0, loads=(0.1, 0.5, 0.9), seed=4, pool=64, capacity_
             "loads": results, "what": "Poisson arrivals, 1..64 frames per request, device-resident LLRs and results"}
 
 
+
+def usable_cores():
+    """CPU model and the cores this process may use: the affinity mask,
+    further limited by a cgroup CPU quota where one is set."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    n = len(os.sched_getaffinity(0))
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fh:
+            q, per = fh.read().split()[:2]
+            if q != "max":
+                quota = float(q) / float(per)
+    except (OSError, ValueError):
+        pass
+    cores = n if quota is None else max(1, min(n, int(quota)))
+    return {"cpu_model": model, "affinity_cpus": n, "cgroup_quota_cpus": quota, "usable": cores}
+
+
+def gen_frames(code, seed, frame_ids, ebn0_db, llr="i8", threads=8):
+    """LLR rows (6-bit int8 or float32) and information bits of the given
+    frame indices of one code."""
+    from paper_1504_00353_amd import inputs, synth
+    l32, info = inputs.channel_frames(code, seed, frame_ids, ebn0_db, threads)
+    return (synth.quantize6(l32) if llr == "i8" else l32), info
+
+
+def timed_launches(fn, reps, stream):
+    """Mean and median of reps launches of fn timed with events on the
+    launch stream (after one untimed launch)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = [a.elapsed_time(b) for a, b in ev]
+    return float(np.mean(ms)), float(np.median(ms)), wall
+
+
+def roof(bytes_per_launch, mean_ms, kernel):
+    gbs = bytes_per_launch / (mean_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 5), "kernel": kernel, "bytes_per_launch": int(bytes_per_launch),
+            "mean_kernel_ms": round(mean_ms, 4)}
+
+
+def single_code_config(wl, reps=10, frames=None):
+    """One workload of a single code: its frames resident, reps launches of
+    the unrolled kernel; information Gb/s, FER and the HBM roofline."""
+    import torch
+    from paper_1504_00353_amd import Code, synth
+    n, k, d = wl["codes"][0]
+    frames = frames or wl["frames"]
+    code = Code(n, k, d, algo=wl["algo"], llr=wl["llr"], kernel="unrolled")
+    llr_np, info = gen_frames(code, wl["seed"], np.arange(frames), wl["ebn0_db"], wl["llr"])
+    llr = torch.from_numpy(llr_np).cuda()
+    out = torch.empty((frames, code.row_bytes), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    mean_ms, med_ms, wall = timed_launches(lambda: code.decode(llr, out=out), reps, stream)
+    fer = float(np.mean((synth.unpack_bits(out.cpu().numpy(), k) != info).any(axis=1)))
+    elem = 1 if wl["llr"] == "i8" else 4
+    bpf = n * elem + (k + 7) // 8
+    res = {"workload": wl["name"], "frames": frames, "algo": wl["algo"], "llr": wl["llr"],
+           "value": round(float(k) * frames * reps / wall / 1e9, 3), "unit": "Gbps",
+           "ms_per_launch": round(mean_ms, 4), "fer": round(fer, 5), "bytes_per_frame": bpf,
+           "roofline": roof(bpf * frames, mean_ms, "polar_unrolled (%s)" % ("int8" if elem == 1 else "float"))}
+    code.close()
+    return res
+
+
+def mixed_distinct_config(reps=5, frames=65536, seed=3):
+    """The mixed workload with every descriptor on its own LLR row: 65,536
+    distinct frames (code uniform over the 15 (N, R) pairs, Eb/N0 uniform
+    2-5 dB per frame), about 715 MB of int8 LLRs, one persistent launch."""
+    import torch
+    from paper_1504_00353_amd import Batch, Code, synth, workloads as W
+    codes = [Code(n, k, d, llr="i8", prepare=False) for n, k, d in W.MIXED["codes"]]
+    batch = Batch(codes)
+    idx = np.arange(frames)
+    cidx, ebn0 = synth.frame_params(seed, idx, [list(range(len(codes))), W.MIXED["ebn0_db"]])
+    cidx = np.asarray(cidx, np.int32)
+    ebn0 = np.asarray(ebn0)
+    sizes = np.array([codes[c].n for c in cidx], np.int64)
+    rb = np.array([codes[c].row_bytes for c in cidx], np.int64)
+    bo = np.concatenate([[0], np.cumsum(rb)[:-1]]).astype(np.int64)
+    llr = torch.empty(int(sizes.sum()), dtype=torch.int8, device="cuda")
+    offs = np.zeros(frames, np.int64)
+    info = [None] * len(codes)
+    sels = []
+    pos = 0
+    for c, code in enumerate(codes):  # each frame its own row; the rows of one code side by side
+        sel = np.flatnonzero(cidx == c)
+        sels.append(sel)
+        if sel.size == 0:
+            continue
+        l, info[c] = gen_frames(code, seed, sel, ebn0[sel])
+        offs[sel] = pos + np.arange(sel.size, dtype=np.int64) * code.n
+        llr[pos:pos + l.size] = torch.from_numpy(l.reshape(-1)).cuda()
+        pos += l.size
+    out = torch.zeros(int(rb.sum()), dtype=torch.uint8, device="cuda")
+    batch.set_frames(cidx, offs, bo)
+    shape = batch.tune(llr, out)
+    stream = torch.cuda.current_stream()
+    mean_ms, med_ms, wall = timed_launches(lambda: batch.decode(llr, out), reps, stream)
+    o = out.cpu().numpy()
+    fe = 0
+    for c, sel in enumerate(sels):
+        if sel.size:
+            rows = np.stack([o[bo[i]:bo[i] + rb[i]] for i in sel])
+            fe += int((synth.unpack_bits(rows, codes[c].k) != info[c]).any(axis=1).sum())
+    ks = np.array([codes[c].k for c in cidx], np.int64)
+    total_bytes = int(sizes.sum() + rb.sum())
+    return {"workload": W.MIXED["name"], "frames": frames, "distinct_frames": frames,
+            "llr_bytes": int(sizes.sum()), "value": round(float(ks.sum()) * reps / wall / 1e9, 3), "unit": "Gbps",
+            "ms_per_launch": round(mean_ms, 4), "fer": round(fe / frames, 5), "launch_shape": shape,
+            "roofline": roof(total_bytes, mean_ms, "polar_batch (int8)")}
+
+
+def stress_config(replays=20, frames=262144, distinct=4096):
+    """Throughput stress: 262,144 frames per launch of (32768,29492) and of
+    (4096,3686), int8, Eb/N0 4.5 dB, the launch captured in a HIP graph and
+    replayed; median replay time.  Every frame has its own LLR row (8 GiB
+    and 1 GiB); the row contents repeat a set of `distinct` generated
+    frames."""
+    import torch
+    from paper_1504_00353_amd import Code, synth, workloads as W
+    wl = W.STRESS
+    res = []
+    for n, k, d in wl["codes"]:
+        code = Code(n, k, d, algo="fastssc", llr="i8", kernel="unrolled")
+        nd = min(distinct * (32768 // n), frames)
+        l_np, info = gen_frames(code, wl["seed"], np.arange(nd), wl["ebn0_db"])
+        src = torch.from_numpy(l_np).cuda()
+        llr = src.repeat(frames // nd, 1)
+        del src
+        out = torch.empty((frames, code.row_bytes), dtype=torch.uint8, device="cuda")
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(2):
+                code.decode(llr, out=out, stream=s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            code.decode(llr, out=out, stream=s)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(replays)]
+        cur = torch.cuda.current_stream()
+        for a, b in ev:
+            a.record(cur)
+            g.replay()
+            b.record(cur)
+        torch.cuda.synchronize()
+        ms = [a.elapsed_time(b) for a, b in ev]
+        med = float(np.median(ms))
+        dec = synth.unpack_bits(out[:nd].cpu().numpy(), k)
+        same = bool(torch.equal(out[:nd], out[nd:2 * nd])) if frames >= 2 * nd else True
+        bpf = n + (k + 7) // 8
+        res.append({"code": [n, k], "frames": frames, "distinct_frames": nd, "replays": replays,
+                    "median_replay_ms": round(med, 4), "value": round(float(k) * frames / (med / 1e3) / 1e9, 3),
+                    "unit": "Gbps", "fer": round(float(np.mean((dec != info).any(axis=1))), 5),
+                    "repeated_rows_equal": same,
+                    "roofline": roof(bpf * frames, float(np.mean(ms)), "polar_unrolled (int8), graph replay")})
+        del llr, out, g
+        torch.cuda.empty_cache()
+        code.close()
+    return {"workload": wl["name"], "codes": res, "what": "hipGraph-captured launch, median of replays"}
+
+
 def percentile(v, p):
     return float(np.percentile(np.asarray(v, np.float64), p))
 
@@ -296,7 +480,7 @@ def cpu_baseline(frozen, llr, seconds=10.0):
     """Plain CPU oracle (int8 Fast-SSC) on this host: all-core throughput
     over repeated passes of a frame sample, plus a one-core latency."""
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
+    threads = usable_cores()["usable"]
     sample = llr[:512]
     # one core
     t0 = time.perf_counter()
@@ -330,6 +514,9 @@ def main():
                          "GPU's steady clock (short runs start below it)")
     ap.add_argument("--kernel", choices=["unrolled", "schedule"], default="unrolled",
                     help="generated per-code kernel (default) or the schedule-interpreting one")
+    ap.add_argument("--only", choices=["sc_f32", "fastssc_f32", "mixed", "stress"], default=None,
+                    help="run just this one workload configuration (profiling) and print its object")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workload configurations")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -345,7 +532,14 @@ def main():
         return
 
     import torch
-    from paper_1504_00353_amd import Code, synth
+    from paper_1504_00353_amd import Code, synth, workloads as W
+
+    config_runs = {"sc_f32": lambda: single_code_config(W.SC_1024),
+                   "fastssc_f32": lambda: single_code_config(W.FSSC_32K_F32),
+                   "mixed": mixed_distinct_config, "stress": stress_config}
+    if args.only:
+        print(json.dumps({args.only: config_runs[args.only]()}), flush=True)
+        return
 
     n, k, design, ebn0 = 32768, 29492, 4.0, 4.0
     frames = args.frames
@@ -503,10 +697,12 @@ def main():
         result["mixed_batch"] = mixed_batch_bench(max(args.steps // 2, 3))
     if not args.no_serving and args.kernel == "unrolled":
         result["serving"] = serving_bench(args.serving_seconds)
+    if not args.no_configs and args.kernel == "unrolled":
+        result["configs"] = {name: run() for name, run in config_runs.items()}
     if not args.no_cpu:
         done, dt, threads, one_core_us = cpu_baseline(frozen, llr_np, args.cpu_seconds)
         result["cpu_baseline"] = {"value": round(done * k / dt / 1e9, 5), "unit": "Gbps", "cores": threads,
-                                  "kind": "oracle",
+                                  "kind": "oracle", "host": usable_cores(),
                                   "sample": "%d frames (512 distinct, repeated) of this workload, int8 Fast-SSC, "
                                             "%.1f s" % (done, dt),
                                   "one_core_latency_us": round(one_core_us, 1)}
