@@ -94,6 +94,12 @@ __device__ __forceinline__ float select_lane(uint64_t m, float a, float b) {
   return r;
 }
 __device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+// Lane J of v set to the wave-uniform x (v_writelane_b32), other lanes kept.
+template <int J>
+__device__ __forceinline__ uint32_t write_lane(uint32_t v, uint32_t x) {
+  asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "i"(J));
+  return v;
+}
 __device__ __forceinline__ float rflf(float x) { return __uint_as_float(rfl(__float_as_uint(x))); }
 // Orders the wave's LDS traffic across lanes and keeps the compiler from
 // moving memory operations over op boundaries.
@@ -101,6 +107,19 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// f(integral_constant<int, 0>) .. f(integral_constant<int, N-1>)
+template <int V>
+struct int_c {
+  static constexpr int value = V;
+};
+template <int N, int I = 0, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(int_c<I>{});
+    static_for<N, I + 1>(f);
+  }
 }
 
 __device__ __forceinline__ uint64_t low_mask(int bits) { return bits >= 64 ? ~0ull : ((1ull << bits) - 1ull); }
@@ -177,8 +196,14 @@ __device__ __forceinline__ s2 fx(s2 a, s2 b) {
   return __builtin_elementwise_max(__builtin_elementwise_min(a, b),
                                    __builtin_elementwise_sub_sat(z, __builtin_elementwise_max(a, b)));
 }
-// g: b + s a, s = +-1 per half (-1 where beta_l = 1); a, b exact
-__device__ __forceinline__ s2 gx(s2 a, s2 b, s2 s) { return sat_lo(__builtin_elementwise_add_sat(b, a * s)); }
+// g: b + s a, s = +-1 per half (-1 where beta_l = 1); a, b exact.  One
+// multiply-add saturated to the 16-bit range (|s a| <= 32512, so the product
+// is exact), then the lower clamp.
+__device__ __forceinline__ s2 gx(s2 a, s2 b, s2 s) {
+  uint32_t d;
+  asm("v_pk_mad_i16 %0, %1, %2, %3 clamp" : "=v"(d) : "v"(as_u(a)), "v"(as_u(s)), "v"(as_u(b)));
+  return sat_lo(as_s2(d));
+}
 __device__ __forceinline__ s2 g0x(s2 a, s2 b) { return sat_lo(__builtin_elementwise_add_sat(b, a)); }
 // channel value -128 read as -127 (exact), for the channel inputs of g
 __device__ __forceinline__ s2 chanx(s2 a) { return sat_lo(a); }
@@ -229,6 +254,15 @@ struct Dec {
   int pend_n;                 // ... and how many (0: none)
 
   __device__ __forceinline__ LDS unsigned char* stage(int s) const { return alpha + ((1 << s) - 128) * P::ELEM; }
+
+  // g sign pairs of the 4 elements whose beta_l bits are bits 4k..4k+3 of
+  // `bits` (int8 table entry; one bit-field extract and one address add)
+  __device__ __forceinline__ u32x2 gsigns(uint32_t bits, int k) const {
+    // (the compiler turns a plain field extract into shift, mask and add)
+    uint32_t e;
+    asm("v_bfe_u32 %0, %1, %2, 4" : "=v"(e) : "v"(bits), "i"(4 * k));
+    return *(const LDS u32x2*)((const LDS unsigned char*)lut + 8 * e);
+  }
 
   // ------------------------------------------------------------- output
   __device__ __forceinline__ void emit(uint64_t w) {
@@ -302,6 +336,38 @@ struct Dec {
     }
   }
 
+  // SPC correction index of a node of size NV <= 64 held one LLR per lane:
+  // the lowest lane among lanes < NV of least |x| (Listing 2's first-match
+  // search).  int8 codes: every value is an integer below 2^7, so the low 16
+  // bits of |x|'s float encoding are zero and hold the lane, and one minimum
+  // over the keys gives both; float codes: the minimum, then the first lane
+  // attaining it.
+  template <int NV>
+  __device__ __forceinline__ int spc_min_lane(float x) const {
+    if constexpr (P::ELEM == 1) {
+      uint32_t key = (__float_as_uint(x) & 0x7fffffffu) | (uint32_t)lane;
+      if constexpr (NV < 64) key = lane < NV ? key : 0xffffffffu;
+      if constexpr (NV >= 64) key = min(key, from_up<32>(key));
+      if constexpr (NV >= 32) key = min(key, from_up<16>(key));
+      if constexpr (NV >= 16) key = min(key, from_up<8>(key));
+      if constexpr (NV >= 8) key = min(key, from_up<4>(key));
+      if constexpr (NV >= 4) key = min(key, from_up<2>(key));
+      if constexpr (NV >= 2) key = min(key, from_up<1>(key));
+      return (int)(rfl(key) & 63u);
+    } else {
+      float v = lane < NV ? fabsf(x) : 3.0e38f;
+      if constexpr (NV >= 64) v = fminf(v, from_up<32>(v));
+      if constexpr (NV >= 32) v = fminf(v, from_up<16>(v));
+      if constexpr (NV >= 16) v = fminf(v, from_up<8>(v));
+      if constexpr (NV >= 8) v = fminf(v, from_up<4>(v));
+      if constexpr (NV >= 4) v = fminf(v, from_up<2>(v));
+      if constexpr (NV >= 2) v = fminf(v, from_up<1>(v));
+      const float mn = rflf(v);
+      const uint64_t cand = ballot(lane < NV && fabsf(x) == mn);
+      return __ffsll((unsigned long long)cand) - 1;
+    }
+  }
+
   __device__ __forceinline__ void set_win(int off, uint64_t m, uint64_t bits) {
     win = (win & ~(m << off)) | (bits << off);
   }
@@ -331,18 +397,7 @@ struct Dec {
       pend_v = bit ? 1ull : 0ull;
       pend_n = 1;
     } else {  // DOP_SPC
-      if (__popcll(hd) & 1) {
-        float v = lane < NV ? fabsf(x) : 3.0e38f;
-        if constexpr (NV >= 64) v = fminf(v, from_up<32>(v));
-        if constexpr (NV >= 32) v = fminf(v, from_up<16>(v));
-        if constexpr (NV >= 16) v = fminf(v, from_up<8>(v));
-        if constexpr (NV >= 8) v = fminf(v, from_up<4>(v));
-        if constexpr (NV >= 4) v = fminf(v, from_up<2>(v));
-        if constexpr (NV >= 2) v = fminf(v, from_up<1>(v));
-        const float mn = rflf(v);
-        const uint64_t cand = ballot(lane < NV && fabsf(x) == mn);
-        hd ^= 1ull << (__ffsll((unsigned long long)cand) - 1);
-      }
+      if (__popcll(hd) & 1) hd ^= 1ull << spc_min_lane<NV>(x);
       set_win(off, m, hd);
       pend_v = transform_node<NV>(hd) >> 1;
       pend_n = NV - 1;
@@ -385,17 +440,7 @@ struct Dec {
     uint64_t out;
     int nout;
     if (spc_right) {
-      if (__popcll(hd) & 1) {
-        float v = lane < H ? fabsf(g) : 3.0e38f;
-        if constexpr (H >= 32) v = fminf(v, from_up<16>(v));
-        if constexpr (H >= 16) v = fminf(v, from_up<8>(v));
-        if constexpr (H >= 8) v = fminf(v, from_up<4>(v));
-        if constexpr (H >= 4) v = fminf(v, from_up<2>(v));
-        if constexpr (H >= 2) v = fminf(v, from_up<1>(v));
-        const float mn = rflf(v);
-        const uint64_t cand = ballot(lane < H && fabsf(g) == mn);
-        hd ^= 1ull << (__ffsll((unsigned long long)cand) - 1);
-      }
+      if (__popcll(hd) & 1) hd ^= 1ull << spc_min_lane<H>(g);
       out = transform_node<H>(hd) >> 1;
       nout = H - 1;
     } else {
@@ -527,7 +572,7 @@ struct Dec {
             rl = fx(al, bl);
             rh = fx(ah, bh);
           } else if constexpr (CODE == DOP_G) {
-            const u32x2 sg = *(const LDS u32x2*)(lut + 2 * ((bb >> (4 * k)) & 15u));
+            const u32x2 sg = gsigns(bb, k);
             rl = gx(al, bl, as_s2(sg[0]));
             rh = gx(ah, bh, as_s2(sg[1]));
           } else {
@@ -806,8 +851,67 @@ struct Dec {
   // without u_0 for SPC) to the output, 64-bit words in parallel.
   // st_stage: an LDS alpha stage free at this leaf, of at least 2^S / 8
   // bytes, used as scratch (default: the stage below the leaf).
+  // Rate-1 or SPC leaf of 128..512 int8 LLRs: lane L reads elements
+  // L + 64m, so the hard decisions of each 64 consecutive elements are one
+  // ballot, in index order; the parity and the SPC correction are scalar
+  // work on those 64-bit words, which then go to lanes (word j to lane j) for
+  // the beta array, u = beta G and the output.  The SPC correction takes the least
+  // key |alpha_i| * 512 + i (lowest index among equal magnitudes, Listing 2).
+  template <int S>
+  __device__ __forceinline__ void leaf_ballot(uint32_t code, int o, int st_stage) {
+    constexpr int NV = 1 << S;
+    constexpr int NM = NV / 64;  // 64-bit words of hard decisions
+    constexpr int NW = NV / 32;
+    static_assert(P::ELEM == 1 && S >= 7 && S <= 9, "int8 leaves of 128..512 LLRs");
+    int x[NM];
+    uint64_t hd[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) {
+      if (S == log2n)
+        x[m] = max((int)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(chr, lane + 64 * m, 0, 0), -127);
+      else
+        x[m] = (int)*(const LDS int8_t*)(stage(S) + lane + 64 * m);
+      hd[m] = ballot(x[m] < 0);
+    }
+    if (tr)
+#pragma unroll
+      for (int m = 0; m < NM; ++m) tr[o + lane + 64 * m] = (Chan)x[m];
+    if (code == DOP_SPC) {
+      int par = 0;
+#pragma unroll
+      for (int m = 0; m < NM; ++m) par ^= __popcll(hd[m]);
+      if (par & 1) {
+        uint32_t key = 0xffffffffu;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) key = min(key, ((uint32_t)abs(x[m]) << 9) | (uint32_t)(lane + 64 * m));
+        key = min(key, from_up<32>(key));
+        key = min(key, from_up<16>(key));
+        key = min(key, from_up<8>(key));
+        key = min(key, from_up<4>(key));
+        key = min(key, from_up<2>(key));
+        key = min(key, from_up<1>(key));
+        const int idx = (int)(rfl(key) & 511u);
+#pragma unroll
+        for (int m = 0; m < NM; ++m)
+          if ((idx >> 6) == m) hd[m] ^= 1ull << (idx & 63);
+      }
+    }
+    // beta words to LDS: lane j stores word j
+    LDS uint32_t* bw = beta + (o >> 5);
+    uint32_t w = 0;
+    static_for<NW>([&](auto j) { w = write_lane<j.value>(w, rfl((uint32_t)(hd[j.value >> 1] >> (32 * (j.value & 1))))); });
+    if (lane < NW) bw[lane] = w;
+    // u = beta G and the output bits from the words in lanes (vector work,
+    // as for the wider leaves)
+    finish_leaf<S, 1>(&w, code, (LDS uint32_t*)stage(st_stage));
+  }
+
   template <int S>
   __device__ __forceinline__ void leaf_r1spc(uint32_t code, int o, int st_stage = S - 1) {
+    if constexpr (P::ELEM == 1 && S >= 7 && S <= 9) {
+      leaf_ballot<S>(code, o, st_stage);
+      return;
+    }
     constexpr int NV = 1 << S;
     constexpr int NW = NV >> 5;                 // 32-bit words: 4 .. 1024
     constexpr int PER = NW >= 64 ? NW / 64 : 1; // words per lane
@@ -1117,9 +1221,10 @@ struct DecU : Dec<P> {
   }
 
   // ------------------------------------------------ wide F / G (int8)
-  // One 32-bit word (4 LLRs) of f, g or g_0R; b4: the 4 beta_l bits (g).
+  // One 32-bit word (4 LLRs) of f, g or g_0R; bits 4k..4k+3 of `bits`: its
+  // beta_l bits (g).
   template <uint32_t CODE, bool CH>
-  __device__ __forceinline__ uint32_t fg_word(uint32_t A, uint32_t Bw, uint32_t b4) const {
+  __device__ __forceinline__ uint32_t fg_word(uint32_t A, uint32_t Bw, uint32_t bits, int k) const {
     s2 al = unpack_lo(A), ah = unpack_hi(A), bl = unpack_lo(Bw), bh = unpack_hi(Bw);
     if constexpr (CH && CODE != DOP_F) {
       al = chanx(al);
@@ -1132,7 +1237,7 @@ struct DecU : Dec<P> {
       rl = fx(al, bl);
       rh = fx(ah, bh);
     } else if constexpr (CODE == DOP_G) {
-      const u32x2 sg = *(const LDS u32x2*)(this->lut + 2 * b4);
+      const u32x2 sg = this->gsigns(bits, k);
       rl = gx(al, bl, as_s2(sg[0]));
       rh = gx(ah, bh, as_s2(sg[1]));
     } else {
@@ -1229,7 +1334,7 @@ struct DecU : Dec<P> {
         if (H >= PERIT || i0 < H) {
           uint32_t Rw[NW];
 #pragma unroll
-          for (int k = 0; k < NW; ++k) Rw[k] = fg_word<CODE, CH>(A[u][k], Bv[u][k], (bb[u] >> (4 * k)) & 15u);
+          for (int k = 0; k < NW; ++k) Rw[k] = fg_word<CODE, CH>(A[u][k], Bv[u][k], bb[u], k);
           if constexpr (DREG) {
 #pragma unroll
             for (int k = 0; k < NW; ++k) rs[R::base(S - 1) + 4 * it + k] = Rw[k];
@@ -1298,8 +1403,8 @@ struct DecU : Dec<P> {
             yl = fx(b0l, b1l);
             yh = fx(b0h, b1h);
           } else if constexpr (YC == DOP_G) {
-            const u32x2 sx = *(const LDS u32x2*)(this->lut + 2 * ((by0[u] >> (4 * k)) & 15u));
-            const u32x2 sy = *(const LDS u32x2*)(this->lut + 2 * ((by1[u] >> (4 * k)) & 15u));
+            const u32x2 sx = this->gsigns(by0[u], k);
+            const u32x2 sy = this->gsigns(by1[u], k);
             xl = gx(a0l, a1l, as_s2(sx[0]));
             xh = gx(a0h, a1h, as_s2(sx[1]));
             yl = gx(b0l, b1l, as_s2(sy[0]));
@@ -1318,7 +1423,7 @@ struct DecU : Dec<P> {
             rl = fx(xl, yl);
             rh = fx(xh, yh);
           } else if constexpr (XC == DOP_G) {
-            const u32x2 sg = *(const LDS u32x2*)(this->lut + 2 * ((bx[u] >> (4 * k)) & 15u));
+            const u32x2 sg = this->gsigns(bx[u], k);
             rl = gx(xl, yl, as_s2(sg[0]));
             rh = gx(xh, yh, as_s2(sg[1]));
           } else {

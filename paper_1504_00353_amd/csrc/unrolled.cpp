@@ -406,6 +406,9 @@ int batch_load(const std::vector<char>& code, hipModule_t& module, hipFunction_t
 int batch_launch(hipFunction_t fn, const void* desc, int nframes, const void* llr, uint8_t* bits, int wave_bytes,
                  int waves_per_block, int blocks, void* stream) {
   const unsigned lds = (unsigned)wave_bytes * (unsigned)waves_per_block;
+  // no more workgroups than the frames need (small batches, server steps)
+  const int need = (nframes + waves_per_block - 1) / waves_per_block;
+  if (blocks > need) blocks = need;
   void* args[] = {(void*)&desc, (void*)&nframes, (void*)&llr, (void*)&bits, (void*)&wave_bytes};
   return (int)hipModuleLaunchKernel(fn, (unsigned)blocks, 1, 1, 64u * (unsigned)waves_per_block, 1, 1, lds,
                                     (hipStream_t)stream, args, nullptr);
