@@ -161,52 +161,84 @@ __device__ __forceinline__ uint32_t transform32(uint32_t x) {
 }
 
 // ---------------------------------------------------------------------------
-// int8 LLRs as packed 16-bit integers scaled by 256 (the byte is the high
-// half of each 16-bit lane); pack4 keeps the high bytes.
+// int8 LLRs on packed 16-bit lanes.  A 32-bit word holds LLRs e0..e3; read
+// as two 16-bit lanes it is (256 e1 + u(e0), 256 e3 + u(e2)), u = the byte
+// as unsigned: the odd LLRs in the high bytes, the even ones as a noise byte
+// below them ("garbled").  The even LLRs are moved up with a zero low byte
+// ("clean": 256 e0, 256 e2).  A lane 256 v + n (0 <= n < 256) stands for v.
 //
-// Exact values are multiples of 256 in [-32512, 32512].  f and g return
-// "loose" values: exact, or 32767 standing for +127 (a saturated sum, or f
-// of two channel values -128).  Their high byte is the exact 8-bit result
-// (the saturating g of Listing 4; f with -128 read as -127), so a loose
-// value may be packed or fed to f as it is, and is clamped (tight) before
-// it feeds g.  The channel value -128 (-32768 here) may feed f directly:
-// f's saturating negation turns two of them into 32767.
+// min and max of such lanes give the min and max of the values, whatever
+// the noise; 255 - x (saturating) stands for -v (channel -128 -> +127); so f
+// = max(min(a, b), 255 - max(a, b)) takes clean or garbled operands and
+// returns garbled ones, -128 read as -127 (eq. (1)).  g = b + s a needs a
+// clean a (the noise would be multiplied) but takes a garbled b: the sum's
+// noise stays below the high byte; it saturates to the 16-bit range and is
+// clamped below at -32512, which is Listing 4's saturation to [-127, 127].
+// Results are packed by their high bytes; no result reads as -128.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ s2 as_s2(uint32_t x) { return __builtin_bit_cast(s2, x); }
 __device__ __forceinline__ uint32_t as_u(s2 x) { return __builtin_bit_cast(uint32_t, x); }
-__device__ __forceinline__ s2 unpack_lo(uint32_t w) { return as_s2(__builtin_amdgcn_perm(0u, w, 0x010c000cu)); }
-__device__ __forceinline__ s2 unpack_hi(uint32_t w) { return as_s2(__builtin_amdgcn_perm(0u, w, 0x030c020cu)); }
-__device__ __forceinline__ uint32_t pack4(s2 lo, s2 hi) {
-  return __builtin_amdgcn_perm(as_u(hi), as_u(lo), 0x07050301u);
+// LLRs e0, e2 of a word, clean
+__device__ __forceinline__ s2 even_lanes(uint32_t w) { return as_s2(__builtin_amdgcn_perm(0u, w, 0x020c000cu)); }
+// LLRs e1, e3 of a word, garbled (the word itself)
+__device__ __forceinline__ s2 odd_lanes(uint32_t w) { return as_s2(w); }
+// the word of four results: high bytes of the even and odd lanes
+__device__ __forceinline__ uint32_t pack_eo(s2 even, s2 odd) {
+  return __builtin_amdgcn_perm(as_u(odd), as_u(even), 0x07030501u);
 }
+// garbled -> clean
+__device__ __forceinline__ s2 clean(s2 r) { return as_s2(as_u(r) & 0xFF00FF00u); }
 // lower clamp of a saturated sum: [-32768, 32767] -> [-32512, 32767]
 __device__ __forceinline__ s2 sat_lo(s2 r) {
   const s2 lo = {(short)-32512, (short)-32512};
   return __builtin_elementwise_max(r, lo);
 }
-// loose -> exact
-__device__ __forceinline__ s2 tight(s2 r) {
-  const s2 hi = {(short)32512, (short)32512};
-  return __builtin_elementwise_min(r, hi);
-}
-// f: sgn(a) sgn(b) min(|a|, |b|) = max(min(a, b), -max(a, b)); a, b loose or
-// channel values
+// f: sgn(a) sgn(b) min(|a|, |b|) = max(min(a, b), -max(a, b))
 __device__ __forceinline__ s2 fx(s2 a, s2 b) {
-  const s2 z = {0, 0};
+  const s2 c255 = {255, 255};
   return __builtin_elementwise_max(__builtin_elementwise_min(a, b),
-                                   __builtin_elementwise_sub_sat(z, __builtin_elementwise_max(a, b)));
+                                   __builtin_elementwise_sub_sat(c255, __builtin_elementwise_max(a, b)));
 }
-// g: b + s a, s = +-1 per half (-1 where beta_l = 1); a, b exact.  One
-// multiply-add saturated to the 16-bit range (|s a| <= 32512, so the product
-// is exact), then the lower clamp.
+// g: b + s a, s = +-1 per lane (-1 where beta_l = 1); a clean, b clean or
+// garbled.  One multiply-add saturated to the 16-bit range (the product is
+// exact), then the lower clamp.
 __device__ __forceinline__ s2 gx(s2 a, s2 b, s2 s) {
   uint32_t d;
   asm("v_pk_mad_i16 %0, %1, %2, %3 clamp" : "=v"(d) : "v"(as_u(a)), "v"(as_u(s)), "v"(as_u(b)));
   return sat_lo(as_s2(d));
 }
 __device__ __forceinline__ s2 g0x(s2 a, s2 b) { return sat_lo(__builtin_elementwise_add_sat(b, a)); }
-// channel value -128 read as -127 (exact), for the channel inputs of g
+// channel value -128 read as -127 (clean or garbled lanes)
 __device__ __forceinline__ s2 chanx(s2 a) { return sat_lo(a); }
+
+// One word (4 LLRs) of f, g or g_0R from words A (alpha_v[i..i+3]) and B
+// (alpha_v[i+h..i+h+3]); sg: the g sign lanes of the even and odd LLRs.
+// CH: A and B are channel words (-128 possible).
+template <uint32_t CODE, bool CH>
+__device__ __forceinline__ uint32_t fg_word_i8(uint32_t A, uint32_t B, u32x2 sg) {
+  s2 ae = even_lanes(A), be = even_lanes(B), ao = odd_lanes(A), bo = odd_lanes(B);
+  if constexpr (CODE != DOP_F) {
+    ao = clean(ao);  // a of g must be clean
+    if constexpr (CH) {
+      ae = chanx(ae);
+      be = chanx(be);
+      ao = chanx(ao);
+      bo = chanx(bo);
+    }
+  }
+  s2 re, ro;
+  if constexpr (CODE == DOP_F) {
+    re = fx(ae, be);
+    ro = fx(ao, bo);
+  } else if constexpr (CODE == DOP_G) {
+    re = gx(ae, be, as_s2(sg[0]));
+    ro = gx(ao, bo, as_s2(sg[1]));
+  } else {
+    re = g0x(ae, be);
+    ro = g0x(ao, bo);
+  }
+  return pack_eo(re, ro);
+}
 
 // ---------------------------------------------------------------------------
 // Arithmetic policies
@@ -559,27 +591,9 @@ struct Dec {
         if constexpr (CODE == DOP_G) bb = beta[(o + i0) >> 5] >> ((o + i0) & 31);
 #pragma unroll
         for (int k = 0; k < NW; ++k) {
-          s2 al = unpack_lo(A[k]), ah = unpack_hi(A[k]);
-          s2 bl = unpack_lo(B[k]), bh = unpack_hi(B[k]);
-          if constexpr (CH && CODE != DOP_F) {
-            al = chanx(al);
-            ah = chanx(ah);
-            bl = chanx(bl);
-            bh = chanx(bh);
-          }
-          s2 rl, rh;
-          if constexpr (CODE == DOP_F) {
-            rl = fx(al, bl);
-            rh = fx(ah, bh);
-          } else if constexpr (CODE == DOP_G) {
-            const u32x2 sg = gsigns(bb, k);
-            rl = gx(al, bl, as_s2(sg[0]));
-            rh = gx(ah, bh, as_s2(sg[1]));
-          } else {
-            rl = g0x(al, bl);
-            rh = g0x(ah, bh);
-          }
-          R[k] = pack4(rl, rh);
+          u32x2 sg = {0u, 0u};
+          if constexpr (CODE == DOP_G) sg = gsigns(bb, k);
+          R[k] = fg_word_i8<CODE, CH>(A[k], B[k], sg);
         }
         if constexpr (CB == 16)
           *(LDS u32x4*)(out + i0) = (u32x4){R[0], R[1], R[2], R[3]};
@@ -1129,10 +1143,11 @@ struct Dec {
     pend_n = 0;
 #pragma unroll
     for (int s = 0; s < 7; ++s) a[s] = 0.0f;
-    // g sign table: entry e (4 beta bits) -> two +-1 pairs
+    // g sign table: entry e (the beta bits of LLRs 0..3 of a word) -> the
+    // +-1 lanes of the even LLRs (0, 2), then of the odd ones (1, 3)
     if (lane < 32) {
-      const int e = lane >> 1, half = lane & 1;
-      const uint32_t b0 = (e >> (2 * half)) & 1u, b1 = (e >> (2 * half + 1)) & 1u;
+      const int e = lane >> 1, odd = lane & 1;
+      const uint32_t b0 = (e >> odd) & 1u, b1 = (e >> (2 + odd)) & 1u;
       lut[lane] = (b0 ? 0x0000FFFFu : 0x00000001u) | (b1 ? 0xFFFF0000u : 0x00010000u);
     }
     // codes of at most 64 bits start in the registers of their root stage
@@ -1225,26 +1240,9 @@ struct DecU : Dec<P> {
   // beta_l bits (g).
   template <uint32_t CODE, bool CH>
   __device__ __forceinline__ uint32_t fg_word(uint32_t A, uint32_t Bw, uint32_t bits, int k) const {
-    s2 al = unpack_lo(A), ah = unpack_hi(A), bl = unpack_lo(Bw), bh = unpack_hi(Bw);
-    if constexpr (CH && CODE != DOP_F) {
-      al = chanx(al);
-      ah = chanx(ah);
-      bl = chanx(bl);
-      bh = chanx(bh);
-    }
-    s2 rl, rh;
-    if constexpr (CODE == DOP_F) {
-      rl = fx(al, bl);
-      rh = fx(ah, bh);
-    } else if constexpr (CODE == DOP_G) {
-      const u32x2 sg = this->gsigns(bits, k);
-      rl = gx(al, bl, as_s2(sg[0]));
-      rh = gx(ah, bh, as_s2(sg[1]));
-    } else {
-      rl = g0x(al, bl);
-      rh = g0x(ah, bh);
-    }
-    return pack4(rl, rh);
+    u32x2 sg = {0u, 0u};
+    if constexpr (CODE == DOP_G) sg = this->gsigns(bits, k);
+    return fg_word_i8<CODE, CH>(A, Bw, sg);
   }
 
   // f / g / g_0R of a node at stage S (8 <= S <= L2N) into stage S-1.  A lane
@@ -1388,49 +1386,48 @@ struct DecU : Dec<P> {
         const int it = b0 + u;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          s2 a0l = unpack_lo(c00[u][k]), a0h = unpack_hi(c00[u][k]);
-          s2 a1l = unpack_lo(c01[u][k]), a1h = unpack_hi(c01[u][k]);
-          s2 b0l = unpack_lo(c10[u][k]), b0h = unpack_hi(c10[u][k]);
-          s2 b1l = unpack_lo(c11[u][k]), b1h = unpack_hi(c11[u][k]);
+          // even LLRs clean, odd ones garbled; the a operands of g clean
+          s2 a0e = even_lanes(c00[u][k]), a1e = even_lanes(c01[u][k]);
+          s2 b0e = even_lanes(c10[u][k]), b1e = even_lanes(c11[u][k]);
+          s2 a0o = odd_lanes(c00[u][k]), a1o = odd_lanes(c01[u][k]);
+          s2 b0o = odd_lanes(c10[u][k]), b1o = odd_lanes(c11[u][k]);
           if constexpr (YC != DOP_F) {  // channel values feeding g
-            a0l = chanx(a0l), a0h = chanx(a0h), a1l = chanx(a1l), a1h = chanx(a1h);
-            b0l = chanx(b0l), b0h = chanx(b0h), b1l = chanx(b1l), b1h = chanx(b1h);
+            a0o = clean(a0o), b0o = clean(b0o);
+            a0e = chanx(a0e), a1e = chanx(a1e), b0e = chanx(b0e), b1e = chanx(b1e);
+            a0o = chanx(a0o), a1o = chanx(a1o), b0o = chanx(b0o), b1o = chanx(b1o);
           }
-          s2 xl, xh, yl, yh;
+          s2 xe, xo, ye, yo;
           if constexpr (YC == DOP_F) {
-            xl = fx(a0l, a1l);
-            xh = fx(a0h, a1h);
-            yl = fx(b0l, b1l);
-            yh = fx(b0h, b1h);
+            xe = fx(a0e, a1e);
+            xo = fx(a0o, a1o);
+            ye = fx(b0e, b1e);
+            yo = fx(b0o, b1o);
           } else if constexpr (YC == DOP_G) {
             const u32x2 sx = this->gsigns(by0[u], k);
             const u32x2 sy = this->gsigns(by1[u], k);
-            xl = gx(a0l, a1l, as_s2(sx[0]));
-            xh = gx(a0h, a1h, as_s2(sx[1]));
-            yl = gx(b0l, b1l, as_s2(sy[0]));
-            yh = gx(b0h, b1h, as_s2(sy[1]));
+            xe = gx(a0e, a1e, as_s2(sx[0]));
+            xo = gx(a0o, a1o, as_s2(sx[1]));
+            ye = gx(b0e, b1e, as_s2(sy[0]));
+            yo = gx(b0o, b1o, as_s2(sy[1]));
           } else {
-            xl = g0x(a0l, a1l);
-            xh = g0x(a0h, a1h);
-            yl = g0x(b0l, b1l);
-            yh = g0x(b0h, b1h);
+            xe = g0x(a0e, a1e);
+            xo = g0x(a0o, a1o);
+            ye = g0x(b0e, b1e);
+            yo = g0x(b0o, b1o);
           }
-          if constexpr (XC != DOP_F) {  // loose values feeding g
-            xl = tight(xl), xh = tight(xh), yl = tight(yl), yh = tight(yh);
-          }
-          s2 rl, rh;
+          s2 re, ro;
           if constexpr (XC == DOP_F) {
-            rl = fx(xl, yl);
-            rh = fx(xh, yh);
-          } else if constexpr (XC == DOP_G) {
+            re = fx(xe, ye);
+            ro = fx(xo, yo);
+          } else if constexpr (XC == DOP_G) {  // the a operand (x) clean
             const u32x2 sg = this->gsigns(bx[u], k);
-            rl = gx(xl, yl, as_s2(sg[0]));
-            rh = gx(xh, yh, as_s2(sg[1]));
+            re = gx(clean(xe), ye, as_s2(sg[0]));
+            ro = gx(clean(xo), yo, as_s2(sg[1]));
           } else {
-            rl = g0x(xl, yl);
-            rh = g0x(xh, yh);
+            re = g0x(clean(xe), ye);
+            ro = g0x(clean(xo), yo);
           }
-          rs[R::base(L2N - 2) + 4 * it + k] = pack4(rl, rh);
+          rs[R::base(L2N - 2) + 4 * it + k] = pack_eo(re, ro);
         }
       }
     }
