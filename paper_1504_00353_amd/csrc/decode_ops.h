@@ -69,7 +69,9 @@ template <int H>
 __device__ __forceinline__ uint32_t from_up(uint32_t x) {
   static_assert(H == 1 || H == 2 || H == 4 || H == 8 || H == 16 || H == 32, "lane distance");
   if constexpr (H <= 8) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x100 + H, 0xf, 0xf, false);  // row_shl:H
+    // row_shl:H; lanes with no source in their row read 0 (bound_ctrl),
+    // so no register has to be zeroed first
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x100 + H, 0xf, 0xf, true);
   } else if constexpr (H == 16) {
     return __builtin_amdgcn_permlane16_swap(x, x, false, false)[1];
   } else {
@@ -324,33 +326,17 @@ struct Dec {
     }
   }
 
-  // Stores 64-bit output word w (index widx in the row), one byte per store
-  // (rows are byte aligned).
-  __device__ __forceinline__ void store_word(int widx, uint64_t w) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int idx = 8 * widx + k;
-      if (idx < row_bytes) row[idx] = (uint8_t)(w >> (8 * k));
-    }
-  }
-
-  // u bits [b, b + 64) of a node whose u is staged as nw 32-bit words at st
-  // (zero past the node).
-  __device__ __forceinline__ uint64_t staged_bits(const LDS uint32_t* st, int nw, int b) const {
-    const int q = b >> 5, r = b & 31;
-    const uint32_t d0 = q < nw ? st[q] : 0u;
-    const uint32_t d1 = q + 1 < nw ? st[q + 1] : 0u;
-    const uint32_t d2 = q + 2 < nw ? st[q + 2] : 0u;
-    const uint64_t lo = (uint64_t)d0 | ((uint64_t)d1 << 32);
-    return r ? (lo >> r) | ((uint64_t)d2 << (64 - r)) : lo;
-  }
-
-  // Output-stream word t after appending u bits [skip, 32 nw) of a staged
-  // node: the stream is the fill bits held in acc, then those u bits.
-  __device__ __forceinline__ uint64_t stream_word(const LDS uint32_t* st, int nw, int t, int skip) const {
-    const int b = 64 * t - fill + skip;
-    if (b < skip) return acc | (staged_bits(st, nw, skip) << fill);  // t == 0, fill > 0
-    return staged_bits(st, nw, b);
+  // Dword d of the output stream of a leaf whose u is staged as 32-bit
+  // words at st: the fill bits held in acc, then u bits from skip on.  A
+  // dword past the node reads staged words past it, which only feed bits
+  // that are cut off (the caller masks them).
+  __device__ __forceinline__ uint32_t stream_dword(const LDS uint32_t* st, int d, int skip) const {
+    const int s = 32 * d - fill + skip;  // u bit at the dword's bit 0
+    if (32 * d >= fill) return __builtin_amdgcn_alignbit(st[(s >> 5) + 1], st[s >> 5], s & 31);
+    const int k = fill - 32 * d;  // acc bits in this dword (d = 0 or 1)
+    const uint32_t a = (uint32_t)(acc >> (32 * d));
+    if (k >= 32) return a;
+    return (a & ((1u << k) - 1u)) | (__builtin_amdgcn_alignbit(st[1], st[0], skip) << k);
   }
 
   // ------------------------------------------------- nodes of size <= 64
@@ -853,8 +839,15 @@ struct Dec {
   __device__ __forceinline__ void xor_up_lanes(uint32_t* wd) {
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
-      const uint32_t p = from_up<D>(wd[m]);
-      if ((lane & D) == 0) wd[m] ^= p;
+      if constexpr (D == 4 || D == 8) {
+        // the lanes with bit D clear are banks 0 and 2 (D = 4) or 0 and 1
+        // (D = 8) of each 16-lane row: a bank-masked DPP move reaches only
+        // them, the others read 0
+        wd[m] ^= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)wd[m], 0x100 + D, 0xf, D == 4 ? 0x5 : 0x3, false);
+      } else {
+        const uint32_t p = from_up<D>(wd[m]);
+        if ((lane & D) == 0) wd[m] ^= p;
+      }
     }
   }
 
@@ -912,7 +905,8 @@ struct Dec {
     }
     // beta words to LDS: lane j stores word j
     LDS uint32_t* bw = beta + (o >> 5);
-    uint32_t w = 0;
+    uint32_t w;
+    asm("" : "=v"(w));  // lanes >= NW are never read: no initial value
     static_for<NW>([&](auto j) { w = write_lane<j.value>(w, rfl((uint32_t)(hd[j.value >> 1] >> (32 * (j.value & 1))))); });
     if (lane < NW) bw[lane] = w;
     // u = beta G and the output bits from the words in lanes (vector work,
@@ -998,11 +992,14 @@ struct Dec {
         if (NW >= 64 || lane < NW) st[lane + 64 * m] = wd[m];
       wave_sync();
       const int total = fill + NV - skip;
-      const int T = total >> 6;
-      for (int t = lane; t < T; t += 64) store_word(words_out + t, stream_word(st, NW, t, skip));
+      const int T = total >> 6;  // whole 64-bit words: inside the row, stored as dwords
+      typedef uint32_t u32_unaligned __attribute__((aligned(1)));
+      for (int d = lane; d < 2 * T; d += 64)
+        *(u32_unaligned*)(row + 8 * words_out + 4 * d) = stream_dword(st, d, skip);
       const int nf = total & 63;
       uint64_t rest = 0;
-      if (nf) rest = stream_word(st, NW, T, skip) & low_mask(nf);  // same words in every lane
+      if (nf)  // same words in every lane
+        rest = (((uint64_t)stream_dword(st, 2 * T + 1, skip) << 32) | stream_dword(st, 2 * T, skip)) & low_mask(nf);
       acc = ((uint64_t)rfl((uint32_t)(rest >> 32)) << 32) | rfl((uint32_t)rest);
       fill = nf;
       words_out += T;
