@@ -421,7 +421,8 @@ def mixed_distinct_config(reps=5, frames=65536, seed=3):
 
 def stress_config(replays=20, frames=262144, distinct=4096):
     """Throughput stress: 262,144 frames per launch of (32768,29492) and of
-    (4096,3686), int8, Eb/N0 4.5 dB, the launch captured in a HIP graph and
+    (4096,3686), int8, Eb/N0 4.5 dB, the register/LDS layout picked by the
+    autotuner on this launch, the launch captured in a HIP graph and
     replayed; median replay time.  Every frame has its own LLR row (8 GiB
     and 1 GiB); the row contents repeat a set of `distinct` generated
     frames."""
@@ -430,13 +431,16 @@ def stress_config(replays=20, frames=262144, distinct=4096):
     wl = W.STRESS
     res = []
     for n, k, d in wl["codes"]:
-        code = Code(n, k, d, algo="fastssc", llr="i8", kernel="unrolled")
+        code = Code(n, k, d, algo="fastssc", llr="i8", kernel="unrolled", prepare=False)
         nd = min(distinct * (32768 // n), frames)
         l_np, info = gen_frames(code, wl["seed"], np.arange(nd), wl["ebn0_db"])
         src = torch.from_numpy(l_np).cuda()
         llr = src.repeat(frames // nd, 1)
         del src
         out = torch.empty((frames, code.row_bytes), dtype=torch.uint8, device="cuda")
+        # the autotuner picks the register/LDS layout on this launch size
+        chosen = code.tune_layout(llr, out=out)
+        layout = dict(code.layouts()[chosen], index=chosen)
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
@@ -461,7 +465,7 @@ def stress_config(replays=20, frames=262144, distinct=4096):
         dec = synth.unpack_bits(out[:nd].cpu().numpy(), k)
         same = bool(torch.equal(out[:nd], out[nd:2 * nd])) if frames >= 2 * nd else True
         bpf = n + (k + 7) // 8
-        res.append({"code": [n, k], "frames": frames, "distinct_frames": nd, "replays": replays,
+        res.append({"code": [n, k], "frames": frames, "distinct_frames": nd, "replays": replays, "layout": layout,
                     "median_replay_ms": round(med, 4), "value": round(float(k) * frames / (med / 1e3) / 1e9, 3),
                     "unit": "Gbps", "fer": round(float(np.mean((dec != info).any(axis=1))), 5),
                     "repeated_rows_equal": same,
@@ -514,6 +518,8 @@ def main():
                          "GPU's steady clock (short runs start below it)")
     ap.add_argument("--kernel", choices=["unrolled", "schedule"], default="unrolled",
                     help="generated per-code kernel (default) or the schedule-interpreting one")
+    ap.add_argument("--layout", type=int, default=0,
+                    help="register/LDS layout of the unrolled kernel (index into Code.layouts(); 0: default rule)")
     ap.add_argument("--only", choices=["sc_f32", "fastssc_f32", "mixed", "stress"], default=None,
                     help="run just this one workload configuration (profiling) and print its object")
     ap.add_argument("--no-configs", action="store_true", help="skip the other workload configurations")
@@ -543,7 +549,8 @@ def main():
 
     n, k, design, ebn0 = 32768, 29492, 4.0, 4.0
     frames = args.frames
-    code = Code(n, k, design, algo="fastssc", llr="i8", kernel=args.kernel)
+    code = Code(n, k, design, algo="fastssc", llr="i8", kernel=args.kernel,
+                layout=args.layout if args.kernel == "unrolled" else 0)
     frozen, info, llr_np = make_inputs(code, seed=2, frames=frames, ebn0_db=ebn0)
     dev = torch.device("cuda", 0)
     llr = torch.from_numpy(llr_np).to(dev)
@@ -677,7 +684,8 @@ def main():
         "data": "synthetic: uniform info bits, BPSK over AWGN at 4.0 dB, 6-bit LLRs in int8",
         "config": {"workload": "fastssc_32768_29492_i8", "N": n, "K": k, "design_ebn0_db": design,
                    "ebn0_db": ebn0, "frames_per_step": frames, "algo": "fast-ssc",
-                   "kernel": args.kernel},
+                   "kernel": args.kernel, "layout": dict(code.layouts()[args.layout], index=args.layout)
+                   if args.kernel == "unrolled" else None},
         "latency_us": None if not lat else
         {"p50": round(percentile(lat, 50), 2), "p99": round(percentile(lat, 99), 2),
          "what": "batched launch of %d frames, submit to completion" % frames},

@@ -134,11 +134,13 @@ polar_status polar_layout_info(const polar_code* code, int index, int* reg_stage
  * POLAR_EINVAL (index out of range), POLAR_ESTATE (prepared). */
 polar_status polar_set_layout(polar_code* code, int index);
 
-/* Autotuner for one code: prepares the code with each layout in turn
- * (compiling kernels not yet in the cache), times decodes of the given
- * frames (device buffers as for polar_decode; bits is overwritten), and
- * leaves the code prepared with the fastest; *chosen (may be NULL)
- * receives its index.  The code must use the unrolled kernel and not be
+/* Autotuner for one code: loads the kernel of every layout (compiling
+ * kernels not yet in the cache), times decodes of the given frames with
+ * each in rounds (device buffers as for polar_decode; bits is
+ * overwritten): warm-up rounds until 30 ms of decoding, then 3 timed
+ * rounds of a burst of 5 back-to-back launches per layout, each layout
+ * keeping its fastest burst; and leaves the code prepared with the
+ * fastest; *chosen (may be NULL) receives its index.  The code must use the unrolled kernel and not be
  * prepared.  Synchronous.  Errors: POLAR_EINVAL, POLAR_ESTATE,
  * POLAR_ECOMPILE, POLAR_EDEVICE, POLAR_ENOMEM (the code is then left
  * unprepared, with the default layout). */

@@ -434,43 +434,76 @@ polar_status polar_tune_layout(polar_code* c, const void* llr, int nframes, uint
   if (c->prepared || c->kernel != POLAR_KERNEL_UNROLLED) return set(POLAR_ESTATE);
   const int count = polar_layout_count(c);
   if (count < 1) return set(POLAR_ENOMEM);
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return set(POLAR_EDEVICE);
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
+  int dev = 0, lds_max = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return set(POLAR_EDEVICE);
-  }
-  int best = 0;
-  float best_ms = -1.0f;
+  // Every candidate's kernel is loaded at once and they are timed in rounds,
+  // so that a clock still ramping up weighs on all of them alike: warm-up
+  // rounds until 30 ms of decoding (at most 64 rounds), then 3 timed rounds
+  // in which each layout runs a burst of 5 back-to-back launches (as in
+  // use: one kernel again and again); each layout keeps its fastest burst.
+  std::vector<polar::UnrolledKernel> ks;
+  std::vector<int> wpb;
+  std::vector<float> best_ms;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   polar_status st = POLAR_OK;
   std::string msg;
-  for (int i = 0; i < count && st == POLAR_OK; ++i) {
-    c->plan.layout = i;
-    st = polar_prepare(c);
-    if (st != POLAR_OK) {
-      msg = g_message;
-      break;
+  try {
+    ks.resize((size_t)count);
+    wpb.resize((size_t)count);
+    best_ms.assign((size_t)count, -1.0f);
+    for (int i = 0; i < count && st == POLAR_OK; ++i) {
+      c->plan.layout = i;
+      std::vector<char> code;
+      if (polar::unrolled_code_object(c->plan, c->llr_type, code, msg) != 0) {
+        st = POLAR_ECOMPILE;
+      } else if (polar::unrolled_load(code, ks[(size_t)i]) != 0) {
+        st = POLAR_EDEVICE;
+      } else {
+        ks[(size_t)i].wave_bytes = polar::unrolled_wave_bytes(c->plan, c->llr_type);
+        const int w = lds_max / ks[(size_t)i].wave_bytes;
+        wpb[(size_t)i] = w < 1 ? 1 : (w > 4 ? 4 : w);
+      }
     }
-    float ms_min = -1.0f;
-    for (int rep = 0; rep < 4 && st == POLAR_OK; ++rep) {  // the first launch warms up
-      if (hipEventRecord(e0, (hipStream_t)stream) != hipSuccess ||
-          polar::unrolled_launch(c->unrolled, llr, nframes, bits, nullptr, c->waves_per_block, stream) != 0 ||
-          hipEventRecord(e1, (hipStream_t)stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+  } catch (const std::bad_alloc&) {
+    st = POLAR_ENOMEM;
+  }
+  if (st == POLAR_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = POLAR_EDEVICE;
+  float warm_ms = 0.0f;
+  int warm_rounds = 0, timed_rounds = 0;
+  while (st == POLAR_OK && timed_rounds < 3) {
+    const bool timed = warm_ms >= 30.0f || warm_rounds >= 64;
+    const int burst = timed ? 5 : 1;
+    for (int i = 0; i < count && st == POLAR_OK; ++i) {
+      if (hipEventRecord(e0, (hipStream_t)stream) != hipSuccess) st = POLAR_EDEVICE;
+      for (int b = 0; b < burst && st == POLAR_OK; ++b)
+        if (polar::unrolled_launch(ks[(size_t)i], llr, nframes, bits, nullptr, wpb[(size_t)i], stream) != 0)
+          st = POLAR_EDEVICE;
+      if (st != POLAR_OK || hipEventRecord(e1, (hipStream_t)stream) != hipSuccess ||
+          hipEventSynchronize(e1) != hipSuccess) {
         st = POLAR_EDEVICE;
         break;
       }
       float ms = 0.0f;
       (void)hipEventElapsedTime(&ms, e0, e1);
-      if (rep > 0 && (ms_min < 0.0f || ms < ms_min)) ms_min = ms;
+      ms /= (float)burst;
+      if (!timed)
+        warm_ms += ms;
+      else if (best_ms[(size_t)i] < 0.0f || ms < best_ms[(size_t)i])
+        best_ms[(size_t)i] = ms;
     }
-    unprepare(c);
-    if (st == POLAR_OK && (best_ms < 0.0f || ms_min < best_ms)) {
-      best_ms = ms_min;
-      best = i;
-    }
+    if (timed)
+      ++timed_rounds;
+    else
+      ++warm_rounds;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (polar::UnrolledKernel& k : ks) polar::unrolled_unload(k);
+  int best = 0;
+  for (int i = 1; i < count && st == POLAR_OK; ++i)
+    if (best_ms[(size_t)i] < best_ms[(size_t)best]) best = i;
   if (st != POLAR_OK) {
     c->plan.layout = 0;
     return msg.empty() ? set(st) : set_msg(st, msg);
@@ -531,6 +564,8 @@ polar_batch* polar_batch_create(const polar_code* const* codes, int ncodes) {
     return nullptr;
   }
   b->waves_per_simd = batch_occupancy(b->wave_bytes, 160 * 1024);
+  for (const polar::Plan& p : b->plans)  // and the register stages of every code's layout
+    b->waves_per_simd = std::min(b->waves_per_simd, polar::unrolled_waves_per_simd(p, b->llr_type));
   set(POLAR_OK);
   return b;
 }

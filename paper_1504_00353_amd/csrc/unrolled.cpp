@@ -138,25 +138,28 @@ bool layout_valid(const Plan& p, int llr_type, UnrolledLayout L) {
 
 }  // namespace
 
+int unrolled_stage_vgprs(const Plan& p, int llr_type, UnrolledLayout L) {
+  const int elem = llr_type == 1 ? 4 : 1;
+  int regs = 0;
+  for (int t = p.log2n - 1 - L.vtop; t > p.log2n - 1 - L.vtop - L.nreg; --t) regs += ((1 << t) * elem) >> 8;
+  return regs;
+}
+
 std::vector<UnrolledLayout> unrolled_layouts(const Plan& p, int llr_type) {
   std::vector<UnrolledLayout> out;
   out.push_back(default_layout(p, llr_type));
-  // {vtop, nreg}; int8 candidates keep their register stages within 64
-  // VGPRs (half the budget of four waves per SIMD), which rules out layouts
-  // that could only spill
-  static const int kTryI8[][2] = {{1, 2}, {1, 1}, {1, 3}, {0, 1}, {0, 2}, {0, 0}};
+  // {vtop, nreg}.  int8 candidates leave room for the decoder's working set
+  // (about 56 VGPRs) at two waves per SIMD or more; layouts of more register
+  // stages are compiled for fewer waves per SIMD (kRegWorkingSet below)
+  static const int kTryI8[][2] = {{1, 2}, {1, 1}, {1, 3}, {0, 1}, {0, 2}, {0, 3}, {0, 0}};
   static const int kTryF32[][2] = {{1, 1}, {1, 0}, {0, 0}};
-  const int ntry = llr_type != 0 ? 3 : 6;
-  for (int i = 0; i < ntry && out.size() < 4; ++i) {
+  const int ntry = llr_type != 0 ? 3 : 7;
+  for (int i = 0; i < ntry && out.size() < 6; ++i) {
     UnrolledLayout L;
     L.vtop = llr_type != 0 ? kTryF32[i][0] : kTryI8[i][0];
     L.nreg = llr_type != 0 ? kTryF32[i][1] : kTryI8[i][1];
     if (!layout_valid(p, llr_type, L)) continue;
-    if (llr_type == 0) {
-      int regs = 0;
-      for (int t = p.log2n - 1 - L.vtop; t > p.log2n - 1 - L.vtop - L.nreg; --t) regs += (1 << t) >> 8;
-      if (regs > 64) continue;
-    }
+    if (llr_type == 0 && unrolled_stage_vgprs(p, llr_type, L) + kRegWorkingSet > 256) continue;
     bool dup = false;
     for (const UnrolledLayout& o : out) dup = dup || (o.vtop == L.vtop && o.nreg == L.nreg);
     if (!dup) out.push_back(L);
@@ -177,14 +180,20 @@ int unrolled_wave_bytes(const Plan& p, int llr_type) {
   return wave_lds_bytes(p.log2n, llr_type == 1 ? 4 : 1, L.nreg + L.vtop);
 }
 
-namespace {
-
-// Waves per SIMD the LDS slot allows (160 KB per CU, 4 SIMDs), 1..4: the
-// register budget the generated kernel is compiled for.
-int waves_per_simd_for(int wave_bytes) {
-  int w = (160 * 1024 / wave_bytes) / 4;
+int unrolled_waves_per_simd(const Plan& p, int llr_type) {
+  // what the LDS slot allows (160 KB per CU, 4 SIMDs) ...
+  int w = (160 * 1024 / unrolled_wave_bytes(p, llr_type)) / 4;
+  // ... and, for int8, what the register stages leave room for
+  if (llr_type == 0) {
+    const int regs = unrolled_stage_vgprs(p, llr_type, unrolled_layout(p, llr_type));
+    const int wr = 512 / (regs + kRegWorkingSet);
+    if (wr < w) w = wr;
+  }
   return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
+
+namespace {
+
 
 // The decoder object and its initialisation for one code.
 std::string decoder_decl(const Plan& p, int llr_type, const char* frame_expr, const char* trace_expr) {
@@ -269,7 +278,7 @@ void append_ops(std::string& s, const Plan& p, int llr_type) {
 
 std::string unrolled_source(const Plan& p, int llr_type) {
   const char* chan = llr_type == 1 ? "float" : "int8_t";
-  const int wps = waves_per_simd_for(unrolled_wave_bytes(p, llr_type));
+  const int wps = unrolled_waves_per_simd(p, llr_type);
   std::string s;
   s.reserve(64 * (size_t)p.nops + 4096);
   s += "// generated: unrolled decoder for one polar code\n";

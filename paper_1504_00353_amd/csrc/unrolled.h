@@ -31,6 +31,14 @@ UnrolledLayout unrolled_layout(const Plan& p, int llr_type);
 std::vector<UnrolledLayout> unrolled_layouts(const Plan& p, int llr_type);
 // LDS bytes of one wavefront of the generated kernel of this plan.
 int unrolled_wave_bytes(const Plan& p, int llr_type);
+// VGPRs of a layout's register stages.
+int unrolled_stage_vgprs(const Plan& p, int llr_type, UnrolledLayout L);
+// VGPRs the int8 decoders need besides their register stages.
+constexpr int kRegWorkingSet = 56;
+// Waves per SIMD the plan's generated kernel is compiled for (its register
+// budget): what its LDS slot allows and, for int8, what its register stages
+// leave room for.  1..4.
+int unrolled_waves_per_simd(const Plan& p, int llr_type);
 
 // HIP source of the two kernels (plain and tracing) for the plan's device
 // schedule and the LLR type (0 int8, 1 float).
