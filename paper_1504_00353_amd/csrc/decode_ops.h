@@ -72,10 +72,13 @@ __device__ __forceinline__ uint32_t from_up(uint32_t x) {
     // row_shl:H; lanes with no source in their row read 0 (bound_ctrl),
     // so no register has to be zeroed first
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x100 + H, 0xf, 0xf, true);
-  } else if constexpr (H == 16) {
-    return __builtin_amdgcn_permlane16_swap(x, x, false, false)[1];
   } else {
-    return __builtin_amdgcn_permlane32_swap(x, x, false, false)[1];
+    // the swap's second operand only receives; leave it undefined so that
+    // x needs one copy, not two
+    uint32_t any;
+    asm("" : "=v"(any));
+    if constexpr (H == 16) return __builtin_amdgcn_permlane16_swap(x, any, false, false)[1];
+    else return __builtin_amdgcn_permlane32_swap(x, any, false, false)[1];
   }
 }
 template <int H>
@@ -84,15 +87,16 @@ __device__ __forceinline__ float from_up(float x) {
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return (uint64_t)__builtin_amdgcn_ballot_w64(p); }
-// Per lane: b if bit `lane` of the wave-uniform mask m is set, else a (one
-// v_cndmask with the mask as its SGPR-pair condition).
-__device__ __forceinline__ float select_lane(uint64_t m, float a, float b) {
+// Per lane: -x if bit `lane` of the wave-uniform mask m is set, else x (one
+// v_cndmask with the mask as its SGPR-pair condition and the negation as a
+// source modifier).
+__device__ __forceinline__ float negate_lanes(uint64_t m, float x) {
   // the mask is wave-uniform; readfirstlane tells the compiler so (and
   // costs nothing when it already lives in scalar registers)
   const uint64_t mu = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32) |
                       (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)m);
   float r;
-  asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(mu));
+  asm("v_cndmask_b32_e64 %0, %1, -%1, %2" : "=v"(r) : "v"(x), "s"(mu));
   return r;
 }
 __device__ __forceinline__ uint32_t rfl(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -348,7 +352,7 @@ struct Dec {
     if (code == DOP_F) {
       a[S - 1] = fmin_sum(x, y);
     } else if (code == DOP_G) {
-      a[S - 1] = P::clamp32(y + select_lane(win >> (o & 63), x, -x));
+      a[S - 1] = P::clamp32(y + negate_lanes(win >> (o & 63), x));
     } else {
       a[S - 1] = P::clamp32(y + x);
     }
@@ -529,7 +533,7 @@ struct Dec {
     if (code == DOP_F)
       a[6] = fmin_sum(x, y);
     else if (code == DOP_G)
-      a[6] = P::clamp32(y + select_lane(win, x, -x));  // beta of the left size-64 child
+      a[6] = P::clamp32(y + negate_lanes(win, x));  // beta of the left size-64 child
     else
       a[6] = P::clamp32(y + x);
   }
