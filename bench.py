@@ -2,8 +2,10 @@
 """Benchmark: Fast-SSC decoding of the (32768, 29492) polar code, int8 LLRs.
 
 One step = one batched decode launch of 4,096 frames (channel LLRs already
-resident in HBM), the workload on which the paper quotes its 26 us / 1.13
-Gb/s single-core figure for this code.  Prints one JSON line:
+resident in HBM; the steps cycle over 4 copies of the frames so that none
+finds its rows in the Infinity Cache), the workload on which the paper
+quotes its 26 us / 1.13 Gb/s single-core figure for this code.  Prints one
+JSON line:
 
   value        information throughput (Gb/s) of the batched decode;
   latency_us   p50/p99 frame latency of a batched launch (submit -> done);
@@ -518,6 +520,10 @@ def main():
                          "GPU's steady clock (short runs start below it)")
     ap.add_argument("--kernel", choices=["unrolled", "schedule"], default="unrolled",
                     help="generated per-code kernel (default) or the schedule-interpreting one")
+    ap.add_argument("--input-copies", type=int, default=4,
+                    help="timed steps cycle over this many copies of the frames at distinct addresses "
+                         "(default 4: 537 MB, more than the 256 MB Infinity Cache, so no step finds its "
+                         "channel rows left in the cache by the step before; 1: the same frames every step)")
     ap.add_argument("--layout", type=int, default=0,
                     help="register/LDS layout of the unrolled kernel (index into Code.layouts(); 0: default rule)")
     ap.add_argument("--only", choices=["sc_f32", "fastssc_f32", "mixed", "stress"], default=None,
@@ -526,6 +532,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
+    if args.input_copies < 1:
+        ap.error("--input-copies must be at least 1")
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py decodes on one GPU only: frames are independent, so more GPUs would "
@@ -554,16 +562,21 @@ def main():
     frozen, info, llr_np = make_inputs(code, seed=2, frames=frames, ebn0_db=ebn0)
     dev = torch.device("cuda", 0)
     llr = torch.from_numpy(llr_np).to(dev)
+    # --input-copies C: the timed steps cycle over C copies of the frames at
+    # distinct device addresses (C x 134 MB); with the default 4 (537 MB) a
+    # step's channel rows are not left in the 256 MB Infinity Cache by the
+    # steps before it
+    llr_steps = [llr] + [llr.clone() for _ in range(args.input_copies - 1)]
     out = torch.empty((frames, code.row_bytes), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
     t_pre = time.perf_counter()
     while time.perf_counter() - t_pre < args.prewarm_seconds:
-        for _ in range(16):
-            code.decode(llr, out=out)
+        for i in range(16):
+            code.decode(llr_steps[i % len(llr_steps)], out=out)
         torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        code.decode(llr, out=out)
+    for i in range(args.warmup):
+        code.decode(llr_steps[i % len(llr_steps)], out=out)
     torch.cuda.synchronize()
 
     # timed region: K batched launches, events on the launch stream
@@ -573,7 +586,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         starts[i].record(stream)
-        code.decode(llr, out=out)
+        code.decode(llr_steps[i % len(llr_steps)], out=out)
         ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -685,7 +698,7 @@ def main():
         "config": {"workload": "fastssc_32768_29492_i8", "N": n, "K": k, "design_ebn0_db": design,
                    "ebn0_db": ebn0, "frames_per_step": frames, "algo": "fast-ssc",
                    "kernel": args.kernel, "layout": dict(code.layouts()[args.layout], index=args.layout)
-                   if args.kernel == "unrolled" else None},
+                   if args.kernel == "unrolled" else None, "input_copies": args.input_copies},
         "latency_us": None if not lat else
         {"p50": round(percentile(lat, 50), 2), "p99": round(percentile(lat, 99), 2),
          "what": "batched launch of %d frames, submit to completion" % frames},
