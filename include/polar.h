@@ -357,9 +357,10 @@ void polar_batch_destroy(polar_batch* batch);
  * retires finished steps (in whatever order they finish), admits what fits
  * and launches steps (batch decodes) over the admitted frames not yet
  * launched while server streams are free: one step per frame length, the
- * length of the oldest admitted request first, so steps overlap on the
- * device, short codes do not wait for long ones, and requests that arrive
- * while steps run join the next.  Each frame is decoded exactly as
+ * length of the oldest admitted request first (at most two steps of one
+ * length in flight, so one busy length cannot hold every stream), so steps
+ * overlap on the device, short codes do not wait for long ones, and
+ * requests that arrive while steps run join the next.  Each frame is decoded exactly as
  * polar_decode would decode it alone.
  * Not thread safe: one thread drives a server, with the server's device
  * current.  After a HIP failure (POLAR_EDEVICE from a poll) the requests in
