@@ -114,18 +114,21 @@ polar_status polar_set_fused_nodes(polar_code* code, int enable);
 polar_status polar_set_kernel(polar_code* code, polar_kernel kernel);
 
 /* Layouts of an unrolled kernel's widest alpha stages (how many stages sit
- * in registers instead of LDS, and whether the stage below the root is
- * recomputed from the channel instead of stored): the choices the
+ * in registers instead of LDS, whether the stage below the root is
+ * recomputed from the channel instead of stored, and -- float codes of
+ * N = 32768 -- whether the stage below the register stage is recomputed
+ * from it instead of stored): the choices the
  * autotuner times, a per-code analogue of the threads-per-block,
  * blocks-per-kernel and shared-memory sweeps of Sec. V (Sec. V-B, V-C,
  * V-E).  Index 0 is the default rule;
  * every layout gives identical results.  polar_layout_count returns how
  * many there are for the code as configured (LLR type; 0 on NULL),
  * polar_layout_info describes one (any output pointer may be NULL;
+ * virtual_top, virtual_mid: 0 or 1 for the two recomputed stages;
  * wave_lds_bytes: LDS per frame).  Errors: POLAR_EINVAL. */
 int polar_layout_count(const polar_code* code);
 polar_status polar_layout_info(const polar_code* code, int index, int* reg_stages, int* virtual_top,
-                               int* wave_lds_bytes);
+                               int* wave_lds_bytes, int* virtual_mid);
 
 /* Selects layout `index` for the code's unrolled kernel (and for batches
  * created from the code afterwards).  Before polar_prepare; polar_configure

@@ -64,7 +64,7 @@ def _lib():
         L.polar_set_fused_nodes.argtypes = [P, I]
         L.polar_device_schedule.argtypes = [P, P, I, P]
         L.polar_layout_count.argtypes = [P]
-        L.polar_layout_info.argtypes = [P, I, P, P, P]
+        L.polar_layout_info.argtypes = [P, I, P, P, P, P]
         L.polar_set_layout.argtypes = [P, I]
         L.polar_tune_layout.argtypes = [P, P, I, P, P, P]
         L.polar_build_kernel.argtypes = [P]
@@ -165,14 +165,15 @@ class Code:
 
     def layouts(self):
         """The unrolled kernel's candidate layouts, the default first: dicts
-        of reg_stages, virtual_top and wave_lds_bytes."""
+        of reg_stages, virtual_top, virtual_mid and wave_lds_bytes."""
         L = _lib()
         out = []
         for i in range(L.polar_layout_count(self._h)):
-            r, v, b = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
-            _check(L.polar_layout_info(self._h, i, ctypes.byref(r), ctypes.byref(v), ctypes.byref(b)),
+            r, v, b, m = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+            _check(L.polar_layout_info(self._h, i, ctypes.byref(r), ctypes.byref(v), ctypes.byref(b), ctypes.byref(m)),
                    "polar_layout_info")
-            out.append({"reg_stages": r.value, "virtual_top": v.value, "wave_lds_bytes": b.value})
+            out.append({"reg_stages": r.value, "virtual_top": v.value, "virtual_mid": m.value,
+                        "wave_lds_bytes": b.value})
         return out
 
     def set_layout(self, index):

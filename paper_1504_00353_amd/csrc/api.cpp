@@ -214,7 +214,7 @@ int polar_layout_count(const polar_code* c) {
 }
 
 polar_status polar_layout_info(const polar_code* c, int index, int* reg_stages, int* virtual_top,
-                               int* wave_lds_bytes) {
+                               int* wave_lds_bytes, int* virtual_mid) {
   if (!c || index < 0) return set(POLAR_EINVAL);
   try {
     const std::vector<polar::UnrolledLayout> all = polar::unrolled_layouts(c->plan, c->llr_type);
@@ -222,8 +222,9 @@ polar_status polar_layout_info(const polar_code* c, int index, int* reg_stages, 
     const polar::UnrolledLayout& L = all[(size_t)index];
     if (reg_stages) *reg_stages = L.nreg;
     if (virtual_top) *virtual_top = L.vtop;
+    if (virtual_mid) *virtual_mid = L.vmid;
     if (wave_lds_bytes)
-      *wave_lds_bytes = polar::wave_lds_bytes(c->plan.log2n, c->llr_type == POLAR_LLR_F32 ? 4 : 1, L.nreg + L.vtop);
+      *wave_lds_bytes = polar::wave_lds_bytes(c->plan.log2n, c->llr_type == POLAR_LLR_F32 ? 4 : 1, L.off_lds());
   } catch (const std::bad_alloc&) {
     return set(POLAR_ENOMEM);
   }

@@ -1213,7 +1213,7 @@ struct RegStages {
 // virtual top stage and keep the stage below it (L2N-2) in registers
 // (fused_top_f32 writes it), which cuts their LDS slot to about a quarter
 // (N = 32768: 132 KB -> 36 KB, four frames per compute unit).
-template <class P, int L2N, int NREG, int VTOP = 0>
+template <class P, int L2N, int NREG, int VTOP = 0, int VMID = 0>
 struct DecU : Dec<P> {
   typedef Dec<P> B;
   typedef RegStages<L2N - 1 - VTOP, NREG, P::ELEM> R;
@@ -1221,10 +1221,16 @@ struct DecU : Dec<P> {
                 "register stages: int8 of >= 2^11 LLRs, or one float stage below a virtual top stage");
   static_assert(VTOP == 0 || (P::ELEM == 1 ? NREG >= 1 : NREG <= 1),
                 "a virtual top stage feeds a register stage (int8) or the top float stage");
+  static_assert(VMID == 0 || (P::ELEM == 4 && VTOP == 1 && NREG == 1 && L2N == 15),
+                "a virtual stage below the float register stage: N = 32768 float codes");
   uint32_t rs[R::total()];
 
+  // VMID = 1: the stage below the register stage (kVMid) is not stored
+  // either: the ops of its nodes (step_mid) recompute their inputs from the
+  // register stage with the parent's op
+  static constexpr int kVMid = L2N - 1 - VTOP - NREG;
   // highest alpha stage in LDS: scratch for leaves at register stages
-  static constexpr int kTopLds = L2N - 1 - VTOP - NREG;
+  static constexpr int kTopLds = L2N - 1 - VTOP - NREG - VMID;
 
   // Gives the registers of stage S new names before an op reads them, so
   // that no unpacked copies made by an earlier op on the same values stay
@@ -1512,10 +1518,104 @@ struct DecU : Dec<P> {
 
   template <uint32_t W, uint32_t YC>
   __device__ __forceinline__ void step_fused() {
+    fresh_lane();
     if constexpr (P::ELEM == 1)
       fused_top<W & 0xffu, YC, (int)(W >> 16)>();
     else
       fused_top_f32<W & 0xffu, YC, (int)(W >> 16)>();
+    wave_sync();
+  }
+
+  // ------------------------------------ virtual stage below the registers
+  // One float f / g / g_0R as the separate ops compute it: a = alpha_v[i],
+  // b = alpha_v[i + h] (bit patterns), `bits`: beta_l of LLRs i .. i+3 from
+  // bit 0 (g), k: which of the four.
+  template <uint32_t C>
+  static __device__ __forceinline__ float op_f32(uint32_t a, uint32_t b, uint32_t bits, int k) {
+    if constexpr (C == DOP_F)
+      return fmin_sum(__uint_as_float(a), __uint_as_float(b));
+    else if constexpr (C == DOP_G)  // b + (-a) is exactly b - a
+      return __fadd_rn(__uint_as_float(b), __uint_as_float(a ^ ((bits << (31 - k)) & 0x80000000u)));
+    else
+      return __fadd_rn(__uint_as_float(b), __uint_as_float(a));
+  }
+
+  // f / g / g_0R (XC) of the node of stage kVMid at offset o, whose LLRs are
+  // YC (the parent's op: f for a left child, g or g_0R for a right one) of
+  // the register stage: alpha[j] = YC(A[j], A[j + H1]), and the output
+  // XC(alpha[j], alpha[j + H2]) goes to LDS stage kVMid - 1.  Same float
+  // operations in the same order as the two separate ops; every operand of
+  // lane L is in lane L (a register stage holds LLRs 4L .. 4L+3 of each
+  // block of 256).
+  template <uint32_t XC, uint32_t YC>
+  __device__ __forceinline__ void fg_mid_f32(int o) {
+    constexpr int H1 = 1 << kVMid, H2 = H1 >> 1;
+    constexpr int NB = H2 / 256;                     // output blocks of 256 LLRs
+    constexpr int RH1 = 4 * (H1 / 256), RH2 = 4 * (H2 / 256);  // register distances of + H1, + H2
+    const int lane = this->lane;
+    const int op = o & ~(2 * H1 - 1);                // the parent, at the register stage
+    LDS float* out = (LDS float*)this->stage(kVMid - 1);
+    // beta bits of LLRs p + 4 L .. p + 4 L + 3 (p a multiple of 256): bits
+    // 4 (L & 7) .. of word p / 32 + L / 8 (one lane offset for every block)
+    const LDS uint32_t* bl = this->beta + (lane >> 3);
+    const int sh = (lane & 7) << 2;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j0 = 256 * b + 4 * lane;
+      uint32_t by0 = 0, by1 = 0, bx = 0;
+      if constexpr (YC == DOP_G) {  // bits of the parent's left child at j and j + H2
+        by0 = bl[(op + 256 * b) >> 5] >> sh;
+        by1 = bl[(op + 256 * b + H2) >> 5] >> sh;
+      }
+      if constexpr (XC == DOP_G) bx = bl[(o + 256 * b) >> 5] >> sh;
+      uint32_t Rv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = R::base(kVMid + 1) + 4 * b + k;
+        const float x = op_f32<YC>(rs[r], rs[r + RH1], by0, k);
+        const float y = op_f32<YC>(rs[r + RH2], rs[r + RH2 + RH1], by1, k);
+        Rv[k] = __float_as_uint(op_f32<XC>(__float_as_uint(x), __float_as_uint(y), bx, k));
+      }
+      *(LDS u32x4*)(out + j0) = (u32x4){Rv[0], Rv[1], Rv[2], Rv[3]};
+    }
+  }
+
+  // Rate-1 or SPC leaf of stage kVMid at offset o, its LLRs YC of the
+  // register stage (as in fg_mid_f32), recomputed where they are read.
+  template <uint32_t YC>
+  __device__ __forceinline__ void leaf_mid_f32(uint32_t code, int o) {
+    constexpr int H1 = 1 << kVMid, RH1 = 4 * (H1 / 256);
+    const int op = o & ~(2 * H1 - 1);
+    const LDS uint32_t* bl = this->beta + (this->lane >> 3);  // as in fg_mid_f32
+    const int sh = (this->lane & 7) << 2;
+    auto val = [&](int b, int k) -> float {
+      uint32_t by = 0;
+      if constexpr (YC == DOP_G) by = bl[(op + 256 * b) >> 5] >> sh;
+      const int r = R::base(kVMid + 1) + 4 * b + k;
+      return op_f32<YC>(rs[r], rs[r + RH1], by, k);
+    };
+    leaf_values_f32<kVMid>(code, o, val);
+  }
+
+  // With VMID the register stage leaves little room: a new name for the
+  // lane index at every op keeps the compiler from computing lane-based
+  // addresses once for the whole kernel and holding them (or spilling them).
+  __device__ __forceinline__ void fresh_lane() {
+    if constexpr (VMID) asm volatile("" : "+v"(this->lane));
+  }
+
+  template <uint32_t W, uint32_t YC>
+  __device__ __forceinline__ void step_mid() {
+    fresh_lane();
+    constexpr uint32_t code = W & 0xffu;
+    static_assert(VMID == 1 && (int)((W >> 8) & 0xffu) == kVMid, "an op of the virtual stage");
+    static_assert(code <= DOP_G0R || code == DOP_R1 || code == DOP_SPC, "f, g, g_0R, Rate-1 or SPC");
+    if constexpr (code <= DOP_G0R) {
+      fg_mid_f32<code, YC>((int)(W >> 16));
+    } else {
+      leaf_mid_f32<YC>(code, (int)(W >> 16));
+      this->settle();
+    }
     wave_sync();
   }
 
@@ -1690,17 +1790,15 @@ struct DecU : Dec<P> {
     constexpr int NV = 1 << S;
     constexpr int NB = NV >> 8;  // blocks of 256 LLRs, 4 registers each
     constexpr int NW = NV >> 5;
-    constexpr int PER = NW / 64;
-    static_assert(PER >= 1, "a float register stage holds >= 2048 LLRs");
     const int lane = this->lane;
     LDS uint32_t* bw = this->beta + (o >> 5);
-    if (this->tr) {
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) this->tr[o + 256 * b + 4 * lane + k] = __uint_as_float(rs[R::base(S) + 4 * b + k]);
-    }
     if (code == DOP_REP) {
+      if (this->tr) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) this->tr[o + 256 * b + 4 * lane + k] = __uint_as_float(rs[R::base(S) + 4 * b + k]);
+      }
       // the halving tree s_i <- s_i + s_{i+d}, d = NV/2 .. 1, one rounded add each
       float v[4 * NB];
 #pragma unroll
@@ -1727,13 +1825,33 @@ struct DecU : Dec<P> {
       this->pend_n = 1;
       return;
     }
+    leaf_values_f32<S>(code, o, [&](int b, int k) { return __uint_as_float(rs[R::base(S) + 4 * b + k]); });
+  }
+
+  // Rate-1 or SPC leaf of 2^S float LLRs in the register-stage order: val(b,
+  // k) is LLR 256 b + 4 L + k of lane L (read as often as needed).
+  template <int S, class V>
+  __device__ __forceinline__ void leaf_values_f32(uint32_t code, int o, const V& val) {
+    constexpr int NV = 1 << S;
+    constexpr int NB = NV >> 8;  // blocks of 256 LLRs
+    constexpr int NW = NV >> 5;
+    constexpr int PER = NW / 64;
+    static_assert(PER >= 1, "a float register-order leaf holds >= 2048 LLRs");
+    const int lane = this->lane;
+    LDS uint32_t* bw = this->beta + (o >> 5);
+    if (this->tr) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) this->tr[o + 256 * b + 4 * lane + k] = val(b, k);
+    }
     // beta words to LDS: in block b, lane L holds the hard decisions of LLRs
     // 4L .. 4L+3, a nibble of word 8b + L/8
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       uint32_t nib = 0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) nib |= (__uint_as_float(rs[R::base(S) + 4 * b + k]) < 0.0f ? 1u : 0u) << k;
+      for (int k = 0; k < 4; ++k) nib |= (val(b, k) < 0.0f ? 1u : 0u) << k;
       uint32_t t = nib << (4 * (lane & 7));
       t |= from_up<4>(t);
       t |= from_up<2>(t);
@@ -1755,7 +1873,7 @@ struct DecU : Dec<P> {
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const float m = fabsf(__uint_as_float(rs[R::base(S) + 4 * b + k]));
+          const float m = fabsf(val(b, k));
           if (m < best) {  // this lane's indices grow in this order
             best = m;
             bi = 256 * b + 4 * lane + k;
@@ -1778,6 +1896,7 @@ struct DecU : Dec<P> {
   // ----------------------------------------------------------- one op
   template <uint32_t W>
   __device__ __forceinline__ void step_c() {
+    fresh_lane();
     constexpr uint32_t code = W & 0xffu;
     constexpr int S = (int)((W >> 8) & 0xffu);
     constexpr int o = (int)(W >> 16);

@@ -107,13 +107,27 @@ bool vtop_allowed(const Plan& p) {
   return true;
 }
 
+// The stage below the float register stage (N = 32768: stage 12) can be
+// virtual when every op on its nodes is f, g, g_0R, a combine, or a Rate-1
+// or SPC leaf (the decoder recomputes those from the register stage).
+bool vmid_allowed(const Plan& p) {
+  if (p.log2n != 15) return false;
+  for (int i = 0; i < p.nops; ++i) {
+    const unsigned code = p.dops[i] & 0xffu, st = (p.dops[i] >> 8) & 0xffu;
+    if (st == (unsigned)p.log2n - 3 && !(code <= DOP_CR0 || code == DOP_R1 || code == DOP_SPC)) return false;
+  }
+  return true;
+}
+
 // The default rule: int8 keeps 2 (N = 32768, below a virtual top stage when
 // allowed) or 1 (N = 16384) stages in registers; float codes of N >= 16384
-// use the virtual top stage and one register stage when allowed.
+// use the virtual top stage and one register stage when allowed, and at
+// N = 32768 the virtual stage below it (a 20 KB slot: two frames per SIMD).
 UnrolledLayout default_layout(const Plan& p, int llr_type) {
   UnrolledLayout L;
   if (llr_type != 0) {
     if (p.log2n >= 14 && vtop_allowed(p)) L.vtop = L.nreg = 1;
+    if (L.vtop && vmid_allowed(p)) L.vmid = 1;
   } else if (p.log2n == 15) {
     L.nreg = 2;
     L.vtop = vtop_allowed(p) ? 1 : 0;
@@ -126,11 +140,12 @@ UnrolledLayout default_layout(const Plan& p, int llr_type) {
 // What the decoder templates accept: int8 register stages of >= 2^11 LLRs,
 // at most 3 (a leaf at a register stage stages its bits in the highest LDS
 // stage), a virtual top stage only above a register stage and for N >= 8192;
-// float: one register stage below a virtual top stage (N >= 16384) or
-// neither.
+// float: one register stage below a virtual top stage (N >= 16384), with or
+// without (N = 32768) the virtual stage below it, or neither.
 bool layout_valid(const Plan& p, int llr_type, UnrolledLayout L) {
-  if (L.vtop < 0 || L.vtop > 1 || L.nreg < 0) return false;
+  if (L.vtop < 0 || L.vtop > 1 || L.nreg < 0 || L.vmid < 0 || L.vmid > 1) return false;
   if (L.vtop && !vtop_allowed(p)) return false;
+  if (L.vmid && (llr_type == 0 || L.vtop != 1 || L.nreg != 1 || !vmid_allowed(p))) return false;
   if (llr_type != 0) return (L.vtop == 0 && L.nreg == 0) || (L.vtop == 1 && L.nreg <= 1 && p.log2n >= 14);
   if (L.nreg == 0) return L.vtop == 0;
   return L.nreg <= 3 && p.log2n - L.vtop - L.nreg >= 11 && (L.vtop == 0 || p.log2n >= 13);
@@ -151,17 +166,19 @@ std::vector<UnrolledLayout> unrolled_layouts(const Plan& p, int llr_type) {
   // {vtop, nreg}.  int8 candidates leave room for the decoder's working set
   // (about 56 VGPRs) at two waves per SIMD or more; layouts of more register
   // stages are compiled for fewer waves per SIMD (kRegWorkingSet below)
-  static const int kTryI8[][2] = {{1, 2}, {1, 1}, {1, 3}, {0, 1}, {0, 2}, {0, 3}, {0, 0}};
-  static const int kTryF32[][2] = {{1, 1}, {1, 0}, {0, 0}};
-  const int ntry = llr_type != 0 ? 3 : 7;
+  static const int kTryI8[][3] = {{1, 2, 0}, {1, 1, 0}, {1, 3, 0}, {0, 1, 0}, {0, 2, 0}, {0, 3, 0}, {0, 0, 0}};
+  static const int kTryF32[][3] = {{1, 1, 1}, {1, 1, 0}, {1, 0, 0}, {0, 0, 0}};
+  const int ntry = llr_type != 0 ? 4 : 7;
   for (int i = 0; i < ntry && out.size() < 6; ++i) {
+    const int* t = llr_type != 0 ? kTryF32[i] : kTryI8[i];
     UnrolledLayout L;
-    L.vtop = llr_type != 0 ? kTryF32[i][0] : kTryI8[i][0];
-    L.nreg = llr_type != 0 ? kTryF32[i][1] : kTryI8[i][1];
+    L.vtop = t[0];
+    L.nreg = t[1];
+    L.vmid = t[2];
     if (!layout_valid(p, llr_type, L)) continue;
     if (llr_type == 0 && unrolled_stage_vgprs(p, llr_type, L) + kRegWorkingSet > 256) continue;
     bool dup = false;
-    for (const UnrolledLayout& o : out) dup = dup || (o.vtop == L.vtop && o.nreg == L.nreg);
+    for (const UnrolledLayout& o : out) dup = dup || (o.vtop == L.vtop && o.nreg == L.nreg && o.vmid == L.vmid);
     if (!dup) out.push_back(L);
   }
   return out;
@@ -177,7 +194,7 @@ UnrolledLayout unrolled_layout(const Plan& p, int llr_type) {
 
 int unrolled_wave_bytes(const Plan& p, int llr_type) {
   const UnrolledLayout L = unrolled_layout(p, llr_type);
-  return wave_lds_bytes(p.log2n, llr_type == 1 ? 4 : 1, L.nreg + L.vtop);
+  return wave_lds_bytes(p.log2n, llr_type == 1 ? 4 : 1, L.off_lds());
 }
 
 int unrolled_waves_per_simd(const Plan& p, int llr_type) {
@@ -201,9 +218,9 @@ std::string decoder_decl(const Plan& p, int llr_type, const char* frame_expr, co
   const char* pol = llr_type == 1 ? "PF32" : "PI8";
   std::string s;
   s += "  polar::DecU<polar::" + std::string(pol) + ", " + std::to_string(p.log2n) + ", " + std::to_string(L.nreg) +
-       ", " + std::to_string(L.vtop) + "> d;\n";
+       ", " + std::to_string(L.vtop) + ", " + std::to_string(L.vmid) + "> d;\n";
   s += "  d.init(base, lane, " + std::to_string(p.log2n) + ", " + std::to_string(p.k) + ", llr, " + frame_expr +
-       ", bits, " + trace_expr + ", " + std::to_string(L.nreg + L.vtop) + ");\n";
+       ", bits, " + trace_expr + ", " + std::to_string(L.off_lds()) + ");\n";
   return s;
 }
 
@@ -243,7 +260,9 @@ void append_ops(std::string& s, const Plan& p, int llr_type) {
     const unsigned code = p.dops[i] & 0xffu;
     const int st = (int)((p.dops[i] >> 8) & 0xffu);
     if (L.vtop && st == p.log2n && code <= DOP_G0R) continue;
-    cost[(size_t)i] = op_cost(code, st, L.vtop && st == p.log2n - 1 && code <= DOP_G0R);
+    if (L.vmid && st == p.log2n - 2 && code <= DOP_G0R) continue;
+    const bool fused = code <= DOP_G0R && ((L.vtop && st == p.log2n - 1) || (L.vmid && st == p.log2n - 3));
+    cost[(size_t)i] = op_cost(code, st, fused);
     total += cost[(size_t)i];
   }
   static const double kSteps[3] = {0.40, 0.65, 0.85};
@@ -251,7 +270,11 @@ void append_ops(std::string& s, const Plan& p, int llr_type) {
   double done = 0.0;
   char line[96];
   s += "  __builtin_amdgcn_s_setprio(3);\n";
-  unsigned root_op = DOP_F;
+  // with vtop, the root's f / g / g_0R emit nothing and the ops of its
+  // children become fused ops; with vmid, likewise the ops of the register
+  // stage's nodes and of their children (f / g / g_0R and Rate-1 / SPC
+  // leaves, which recompute their LLRs with the parent's op)
+  unsigned root_op = DOP_F, mid_op = DOP_F;
   for (int i = 0; i < p.nops; ++i) {
     const unsigned w = p.dops[i];
     const unsigned code = w & 0xffu;
@@ -260,8 +283,14 @@ void append_ops(std::string& s, const Plan& p, int llr_type) {
       root_op = code;
       continue;
     }
+    if (L.vmid && st == p.log2n - 2 && code <= DOP_G0R) {
+      mid_op = code;
+      continue;
+    }
     if (L.vtop && st == p.log2n - 1 && code <= DOP_G0R)
       snprintf(line, sizeof line, "  d.template step_fused<0x%08xu, %uu>();\n", w, root_op);
+    else if (L.vmid && st == p.log2n - 3 && (code <= DOP_G0R || code == DOP_R1 || code == DOP_SPC))
+      snprintf(line, sizeof line, "  d.template step_mid<0x%08xu, %uu>();\n", w, mid_op);
     else
       snprintf(line, sizeof line, "  d.template step_c<0x%08xu>();\n", w);
     s += line;

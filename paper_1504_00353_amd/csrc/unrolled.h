@@ -18,10 +18,14 @@ struct UnrolledKernel {
 };
 
 // How a generated kernel places the widest alpha stages: nreg stages in
-// registers, and with vtop the stage below the root not stored at all.
+// registers, with vtop the stage below the root not stored at all, and with
+// vmid (float, N = 32768) not the stage below the register stage either.
 struct UnrolledLayout {
   int nreg = 0;
   int vtop = 0;
+  int vmid = 0;
+  // top stages that are not in LDS
+  int off_lds() const { return nreg + vtop + vmid; }
 };
 // The layout the plan's kernel uses: candidate p.layout of
 // unrolled_layouts() (0, the default rule, when out of range).

@@ -63,6 +63,7 @@ UNROLLED_LAYOUTS = [
     (32768, 29492, 4.0, "fastssc", "i8"),
     (4096, 3686, 4.0, "fastssc", "i8"),
     (16384, 14746, 4.0, "fastssc", "f32"),
+    (32768, 29492, 4.0, "fastssc", "f32"),
 ]
 
 # a batch whose codes use non-default layouts: (N, K, design dB, layout)
@@ -144,10 +145,16 @@ UNROLLED_MASKS = {
     "m32k_r014_spc13_rep13": (32768, _blocks(32768, [("R0", 16384), ("SPC", 8192), ("REP", 8192)])),
     "m32k_spc13_rep13_r013_r113": (32768, _blocks(32768, [("SPC", 8192), ("REP", 8192), ("R0", 8192),
                                                             ("R1", 8192)])),
+    # Rate-1 and SPC leaves of size 4096 and inner size-4096 nodes under each
+    # parent op (f, g, g_0R): the float N = 32768 kernels recompute stage 12
+    "m32k_mid_leaves": (32768, _blocks(32768, [("REP", 2048), ("SPC", 2048), ("R1", 4096), ("SPC", 4096),
+                                               ("R0", 2048), ("SPC", 2048), ("R0", 4096), ("SPC", 4096),
+                                               ("REP", 2048), ("R1", 2048), ("REP", 2048), ("SPC", 2048)])),
     "m16k_spc13_rep13": (16384, _blocks(16384, [("SPC", 8192), ("REP", 8192)])),
     "m16k_r113_spc13": (16384, _blocks(16384, [("R1", 8192), ("SPC", 8192)])),
 }
 
 # masks whose generated kernels are also built for float LLRs (virtual top
 # stage with g_0R and inner children, and a code that keeps the stage)
-UNROLLED_MASKS_F32 = ["m32k_spc13_rep13_r013_r113", "m32k_r014_spc13_rep13", "m32k_r013_r113_rep14"]
+UNROLLED_MASKS_F32 = ["m32k_spc13_rep13_r013_r113", "m32k_r014_spc13_rep13", "m32k_r013_r113_rep14",
+                      "m32k_mid_leaves"]

@@ -249,19 +249,26 @@ def test_layout_candidates_and_arguments():
     L = binding.lib()
     c = binding.Code(32768, 29492, 4.0, prepare=False, kernel="unrolled")
     lay = c.layouts()
-    assert lay[0] == {"reg_stages": 2, "virtual_top": 1, "wave_lds_bytes": 8192}
+    assert lay[0] == {"reg_stages": 2, "virtual_top": 1, "virtual_mid": 0, "wave_lds_bytes": 8192}
     assert len(lay) == len({(x["reg_stages"], x["virtual_top"]) for x in lay})
     for x in lay:  # int8: register stages of >= 2^11 LLRs, at most 3
         assert 1 <= x["reg_stages"] <= 3 and 15 - x["virtual_top"] - x["reg_stages"] >= 11
+        assert x["virtual_mid"] == 0
     f = binding.Code(32768, 29492, 4.0, llr="f32", prepare=False, kernel="unrolled")
-    assert f.layouts()[0] == {"reg_stages": 1, "virtual_top": 1, "wave_lds_bytes": 36480}
-    assert all(x["reg_stages"] <= x["virtual_top"] for x in f.layouts())
+    fl = f.layouts()
+    # float N = 32768: stage 14 and stage 12 recomputed, stage 13 in registers,
+    # stages 7..11 (15,872 B) + sign table + beta in LDS
+    assert fl[0] == {"reg_stages": 1, "virtual_top": 1, "virtual_mid": 1, "wave_lds_bytes": 20096}
+    assert fl[1] == {"reg_stages": 1, "virtual_top": 1, "virtual_mid": 0, "wave_lds_bytes": 36480}
+    assert all(x["reg_stages"] <= x["virtual_top"] and x["virtual_mid"] <= x["reg_stages"] for x in fl)
+    h = binding.Code(16384, 14746, 4.0, llr="f32", prepare=False, kernel="unrolled")
+    assert all(x["virtual_mid"] == 0 for x in h.layouts())
     s = binding.Code(1024, 512, 2.5, prepare=False, kernel="unrolled")
-    assert s.layouts() == [{"reg_stages": 0, "virtual_top": 0, "wave_lds_bytes": 1152}]
+    assert s.layouts() == [{"reg_stages": 0, "virtual_top": 0, "virtual_mid": 0, "wave_lds_bytes": 1152}]
     assert L.polar_layout_count(None) == 0
     assert L.polar_set_layout(c.handle, -1) == binding.EINVAL
     assert L.polar_set_layout(c.handle, len(lay)) == binding.EINVAL
-    assert L.polar_layout_info(c.handle, len(lay), None, None, None) == binding.EINVAL
+    assert L.polar_layout_info(c.handle, len(lay), None, None, None, None) == binding.EINVAL
     assert L.polar_set_layout(c.handle, len(lay) - 1) == binding.OK
     assert L.polar_tune_layout(c.handle, None, 1, None, None, None) == binding.EINVAL
     assert L.polar_tune_layout(c.handle, ctypes.c_void_p(18), 1, ctypes.c_void_p(16), None, None) == binding.EINVAL
@@ -284,11 +291,11 @@ def test_configure_resets_layout():
     chosen in; reconfiguring returns to the default."""
     L = binding.lib()
     c = binding.Code(32768, 29492, 4.0, prepare=False, kernel="unrolled", layout=3)
-    assert L.polar_configure(c.handle, 0, 1) == binding.OK  # float LLRs: 3 candidates
-    assert L.polar_layout_count(c.handle) == 3
-    assert L.polar_set_layout(c.handle, 2) == binding.OK
+    assert L.polar_configure(c.handle, 0, 1) == binding.OK  # float LLRs: 4 candidates
+    assert L.polar_layout_count(c.handle) == 4
+    assert L.polar_set_layout(c.handle, 3) == binding.OK
     assert L.polar_set_fused_nodes(c.handle, 0) == binding.OK
-    assert L.polar_set_layout(c.handle, 3) == binding.EINVAL
+    assert L.polar_set_layout(c.handle, 4) == binding.EINVAL
 
 
 def test_allocation_failure_hook_objects():
