@@ -69,6 +69,10 @@ UNROLLED_LAYOUTS = [
 # a batch whose codes use non-default layouts: (N, K, design dB, layout)
 BATCH_LAYOUTS = [(32768, 29492, 4.0, 2), (4096, 3686, 4.0, 1), (1024, 512, 2.5, 0)]
 
+# a float batch with the N = 32768 code in its default layout (stages 14 and
+# 12 recomputed) beside smaller codes
+BATCH_F32 = [(32768, 29492, 4.0), (4096, 3686, 4.0), (1024, 512, 2.5)]
+
 # unrolled kernels built with the fused leaf-pair nodes switched off (the
 # fused-vs-separate comparison)
 UNROLLED_UNFUSED = [

@@ -167,3 +167,21 @@ def test_batch_of_codes_with_layouts():
     bad = [i for i in range(len(rows)) if not np.array_equal(rows[i], exp[i])]
     assert not bad, "%d frames differ, first %s" % (len(bad), bad[:5])
     batch.close()
+
+
+def test_float_batch_with_virtual_stage():
+    """A float batch whose (32768,29492) code runs with stage 12 recomputed
+    from its register stage (and stage 14 from the channel) beside smaller
+    codes: every frame equals the float32 oracle."""
+    codes = [Code(n, k, d, llr="f32", prepare=False) for n, k, d in workloads.BATCH_F32]
+    assert codes[0].layouts()[0]["virtual_mid"] == 1
+    batch = Batch(codes)
+    frozens = [c.frozen() for c in codes]
+    code_idx, offs, flat, _ = make_mixed(frozens, 78, 200, (3.0, 5.0), llr="f32")
+    assert (code_idx == 0).sum() > 10
+    rows, _, _ = run(batch, codes, code_idx, offs, flat)
+    exp = expected_rows(frozens, code_idx, flat, offs)
+    bad = [i for i in range(len(rows)) if not np.array_equal(rows[i], exp[i])]
+    assert not bad, "%d frames differ, first %s" % (len(bad), bad[:5])
+    batch.close()
+
