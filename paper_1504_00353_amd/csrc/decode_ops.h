@@ -1212,7 +1212,9 @@ struct RegStages {
 // LDS (N = 32768), four frames per SIMD.  Float codes of N >= 16384 use the
 // virtual top stage and keep the stage below it (L2N-2) in registers
 // (fused_top_f32 writes it), which cuts their LDS slot to about a quarter
-// (N = 32768: 132 KB -> 36 KB, four frames per compute unit).
+// (N = 32768: 132 KB -> 36 KB, four frames per compute unit).  VMID = 1
+// (float, N = 32768) does not store the stage below that register stage
+// either (20 KB, eight frames per compute unit).
 template <class P, int L2N, int NREG, int VTOP = 0, int VMID = 0>
 struct DecU : Dec<P> {
   typedef Dec<P> B;
